@@ -1,0 +1,156 @@
+"""Pins of the CPU ladder oracle (eq. pp-Ladder-0 with eq. RIM) against facts that
+do not depend on it: a hand-worked example, closed forms, exact scaling,
+symmetry and equivariance, and the paper's own dressed-integral form."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ccsd as oc
+from oracle import native
+from paper_1810_08142_amd.synthetic import draw_matrix, draw_pair_symmetric, draw_system
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_hand_worked_example():
+    B = np.array([[[1.0, 2.0], [3.0, 4.0]]])
+    tau = np.array([[[[1.0, 5.0], [5.0, 2.0]]]])
+    R = native.ppl(B, tau)
+    rows = np.loadtxt(os.path.join(HERE, "golden", "ppl_hand_2x2.txt"))
+    for a, b, val in rows:
+        assert R[0, 0, int(a), int(b)] == val
+
+
+def test_rank_one_closed_form():
+    # one auxiliary function, B^0_ac = u_a w_c (not symmetric): (ac|bd) = u_a w_c u_b w_d,
+    # so R^{ab}_{ij} = u_a u_b (w^T tau_ij w).  A transposed factor or a swapped
+    # integral index gives w_a w_b (u^T tau u) or u_a w_b (...) instead.
+    o, v = 3, 7
+    u = draw_matrix(v, 11)
+    w = draw_matrix(v, 12)
+    B = np.outer(u, w)[None]
+    tau = draw_pair_symmetric(o, v, 13)
+    R = native.ppl(B, tau)
+    expect = np.einsum("a,b,ijcd,c,d->ijab", u, u, tau, w, w)
+    np.testing.assert_allclose(R, expect, rtol=1e-13, atol=1e-13 * np.abs(expect).max())
+
+
+def test_diagonal_factor_closed_form():
+    # B^Q_ac = delta_ac x^Q_a  =>  R^{ab}_{ij} = (sum_Q x^Q_a x^Q_b) tau^{ab}_{ij}
+    o, v, naux = 3, 6, 5
+    x = draw_matrix((naux, v), 21)
+    B = np.zeros((naux, v, v))
+    for q in range(naux):
+        B[q] = np.diag(x[q])
+    tau = draw_pair_symmetric(o, v, 22)
+    R = native.ppl(B, tau)
+    X = x.T @ x
+    np.testing.assert_allclose(R, X[None, None] * tau, rtol=1e-14, atol=1e-14 * np.abs(R).max())
+
+
+def test_unit_tau_selects_integrals():
+    # pair-symmetric tau with only tau^{cd}_{ij} = tau^{dc}_{ji} = 1 (i != j) gives
+    # R^{ab}_{ij} = (ac|bd) and R^{ab}_{ji} = (ad|bc); for i = j their sum.
+    s = draw_system(2, 5, 4, seed=31)
+    B = s.B_vv
+    o, v = 2, 5
+
+    def ac_bd(a, c, b, d):
+        return sum(B[q, a, c] * B[q, b, d] for q in range(B.shape[0]))
+
+    c, d = 1, 3
+    tau = np.zeros((o, o, v, v))
+    tau[0, 1, c, d] = tau[1, 0, d, c] = 1.0
+    R = native.ppl(B, tau)
+    for a in range(v):
+        for b in range(v):
+            assert abs(R[0, 1, a, b] - ac_bd(a, c, b, d)) <= 1e-15
+            assert abs(R[1, 0, a, b] - ac_bd(a, d, b, c)) <= 1e-15
+    tau = np.zeros((o, o, v, v))
+    tau[1, 1, c, d] = tau[1, 1, d, c] = 1.0
+    R = native.ppl(B, tau)
+    for a in range(v):
+        for b in range(v):
+            assert abs(R[1, 1, a, b] - ac_bd(a, c, b, d) - ac_bd(a, d, b, c)) <= 1e-15
+
+
+def test_pair_symmetry_of_result():
+    # L^{ab}_{ij} = L^{ba}_{ji} when tau has the same symmetry (Sec. II.C)
+    s = draw_system(3, 9, 10, seed=41)
+    tau = draw_pair_symmetric(3, 9, 42)
+    R = native.ppl(s.B_vv, tau)
+    np.testing.assert_allclose(R, R.transpose(1, 0, 3, 2), rtol=0, atol=1e-14 * np.abs(R).max())
+
+
+def test_power_of_two_scaling_is_exact():
+    s = draw_system(2, 6, 7, seed=51)
+    tau = draw_pair_symmetric(2, 6, 52)
+    R = native.ppl(s.B_vv, tau)
+    R2 = native.ppl(s.B_vv * 4.0, tau * 0.5)         # 2^(2*2 - 1) = 8
+    assert np.array_equal(R2, 8.0 * R)
+
+
+def test_permutation_equivariance():
+    o, v = 2, 7
+    s = draw_system(o, v, 6, seed=61)
+    tau = draw_pair_symmetric(o, v, 62)
+    perm = np.random.default_rng(63).permutation(v)
+    R = native.ppl(s.B_vv, tau)
+    Bp = s.B_vv[:, perm][:, :, perm]
+    taup = tau[:, :, perm][:, :, :, perm]
+    Rp = native.ppl(Bp, taup)
+    np.testing.assert_allclose(Rp, R[:, :, perm][:, :, :, perm], rtol=0, atol=1e-13 * np.abs(R).max())
+
+
+def test_linear_in_tau_and_accumulates():
+    s = draw_system(2, 5, 4, seed=71)
+    t1 = draw_pair_symmetric(2, 5, 72)
+    t2 = draw_pair_symmetric(2, 5, 73)
+    R0 = draw_matrix((2, 2, 5, 5), 74)
+    R = native.ppl(s.B_vv, t1, R0.copy())
+    R = native.ppl(s.B_vv, t2, R)
+    Rs = native.ppl(s.B_vv, t1 + t2)
+    np.testing.assert_allclose(R - R0, Rs, rtol=0, atol=1e-14 * np.abs(Rs).max())
+
+
+def test_c_loops_equal_tensor_contraction():
+    # brute force through the explicit v^4 integral tensor (a separate code path)
+    s = draw_system(3, 10, 12, seed=81)
+    tau = draw_pair_symmetric(3, 10, 82)
+    R = native.ppl(s.B_vv, tau)
+    E = oc.ppl(s.B_vv, tau)
+    np.testing.assert_allclose(R, E, rtol=0, atol=1e-13 * np.abs(E).max())
+
+
+def test_pairs_entry_matches_full():
+    s = draw_system(3, 8, 9, seed=91)
+    tau = draw_pair_symmetric(3, 8, 92)
+    R = native.ppl(s.B_vv, tau)
+    pairs = [(0, 0), (7, 1), (3, 5), (7, 7)]
+    out = native.ppl_pairs(s.B_vv, tau, pairs)
+    for k, (a, b) in enumerate(pairs):
+        assert np.array_equal(out[k], R[:, :, a, b])
+
+
+def test_paper_dressed_form_equals_dressed_factors_minus_oo_term():
+    # b^{ab}_{cd} of eq. pp-Ladder-1 against the symmetric dressing B~ = (1-t) B (1+t):
+    # sum_cd b tau = sum_cd (a~c|b~d) tau - sum_kl t^a_k t^b_l sum_cd (kc|ld) tau^{cd}_{ij}
+    o, v = 2, 6
+    s = draw_system(o, v, 8, seed=95, scale=0.2)
+    t1 = draw_matrix((o, v), 96, 0.1)
+    tau = draw_pair_symmetric(o, v, 97)
+    L_paper = oc.ppl_paper_b(s.B_vv, s.B_ov, t1, tau)
+    Bd = oc.dress(s.B, t1)
+    L_dressed = native.ppl(np.ascontiguousarray(Bd[:, o:, o:]), tau)
+    g = oc.eri(s.B_ov, s.B_ov)                       # (kc|ld)
+    W = np.einsum("kcld,ijcd->klij", g, tau)
+    X = np.einsum("ka,lb,klij->ijab", t1, t1, W)
+    np.testing.assert_allclose(L_paper, L_dressed - X, rtol=0, atol=1e-13 * np.abs(L_paper).max())
+
+
+def test_rejects_bad_arguments():
+    B = np.zeros((2, 3, 3))
+    tau = np.zeros((1, 1, 3, 3))
+    with pytest.raises(RuntimeError):
+        native.ppl_pairs(B, tau, [(0, 3)])
