@@ -1,0 +1,96 @@
+/*
+ * riccsd.h -- C ABI of the closed-shell RI-CCSD library for MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ *  - Array arguments are DEVICE pointers owned by the caller (for example the
+ *    data pointer of a device tensor); the library never frees caller memory.
+ *    Arrays are C-contiguous (row-major) and FP64 unless stated otherwise.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the legacy default stream).
+ *    Calls enqueue work on it and return without synchronising, except where a
+ *    host-side scalar result is documented (those synchronise `stream`).
+ *  - Index conventions: MOs occupied first; B[Q][p][q] are the RI factors of
+ *    the MO integrals, (pq|rs) = sum_Q B^Q_pq B^Q_rs (eq. RIM), and
+ *    v^{pq}_{rs} = (pr|qs) (eq. eri).  t1[i][a] = t^a_i, t2[i][j][a][b] = t^{ab}_{ij}.
+ *  - Every call returns a status (RI_OK on success).  On failure nothing is
+ *    enqueued unless the status is RI_E_HIP; ri_last_error_msg() describes the
+ *    failure of the calling thread's most recent call.  No exception crosses
+ *    the ABI and the library never aborts the process.
+ */
+#ifndef RICCSD_H
+#define RICCSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define RI_OK 0
+#define RI_E_ARG 1         /* null pointer, non-positive size, overflow, bad enum */
+#define RI_E_ALIAS 2       /* an output overlaps an input */
+#define RI_E_NOMEM 3       /* device workspace allocation failed or workspace too small */
+#define RI_E_HIP 4         /* HIP runtime or launch error (see ri_last_hip_error) */
+#define RI_E_NOCONV 5      /* iteration limit reached; amplitudes are valid */
+#define RI_E_NUMERIC 6     /* NaN/Inf or divergence detected */
+#define RI_E_UNSUPPORTED 7 /* precision or device not supported */
+
+/* ladder arithmetic */
+#define RI_PREC_FP64 0     /* FP64 MFMA throughout */
+#define RI_PREC_FP32 1     /* FP32 MFMA, FP32 accumulation */
+#define RI_PREC_BF16X3 2   /* bf16 hi+lo split, three products, FP32 accumulation */
+
+const char* ri_status_str(int status);
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char* ri_last_error_msg(void);
+/* hipError_t value of the calling thread's most recent RI_E_HIP failure. */
+int ri_last_hip_error(void);
+
+/*
+ * Particle-particle ladder (Sec. II.C, eq. pp-Ladder-0):
+ *
+ *     R[i][j][a][b] += sum_{c,d} (ac|bd) tau[i][j][c][d],
+ *     (ac|bd)        = sum_Q B_vv[Q][a][c] B_vv[Q][b][d].
+ *
+ * B_vv : [naux][v][v]; the first virtual index is the external one (it matters
+ *        when the factors are t1-dressed and therefore not symmetric).
+ * tau  : [o][o][v][v], tau[i][j][c][d] = tau^{cd}_{ij} (eq. pp-Ladder-01).  The
+ *        result is exact for the pair-symmetric part
+ *        (tau[i][j][c][d] + tau[j][i][d][c]) / 2, which is tau itself for CCSD
+ *        amplitudes (Sec. II.C); R therefore always satisfies
+ *        R^{ab}_{ij} = R^{ba}_{ji} for the added part.
+ * R    : [o][o][v][v], accumulated; must not overlap B_vv or tau (RI_E_ALIAS).
+ * The v^4 integral tensor is never stored: it is rebuilt tile by tile from B_vv
+ * and contracted with symmetric/antisymmetric packed tau (Scuseria's split,
+ * Sec. II.C).  Workspace is allocated stream-ordered on `stream` and released
+ * before the call returns control of it to the stream.  Deterministic: the same
+ * inputs give bitwise the same R.
+ */
+int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
+           void* stream);
+
+/* As ri_ppl with a choice of arithmetic (RI_PREC_*) and an optional caller
+ * workspace: ws == NULL allocates internally; otherwise ws must be 256-byte
+ * aligned and ws_bytes >= ri_ppl_workspace_bytes(o, v, naux, precision)
+ * (RI_E_NOMEM if smaller).  The workspace contents are scratch. */
+int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
+              int precision, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes ri_ppl_ex needs for these sizes (0 on invalid arguments). */
+size_t ri_ppl_workspace_bytes(int o, int v, int naux, int precision);
+
+/* Algorithmic floating-point operation count of one ladder call as executed
+ * (the a<=b half of the integral build plus the packed contraction; one fused
+ * multiply-add counts two).  0 on invalid arguments. */
+double ri_ppl_flops(int o, int v, int naux);
+
+/* tau[i][j][a][b] = t2[i][j][a][b] + t1[i][a] t1[j][b]   (eq. pp-Ladder-01).
+ * t1: [o][v], t2 and tau: [o][o][v][v]; tau may alias t2 (in place). */
+int ri_build_tau(const double* t1, const double* t2, int o, int v, double* tau, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RICCSD_H */

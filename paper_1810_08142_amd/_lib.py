@@ -1,0 +1,61 @@
+"""ctypes binding of ``libriccsd.so`` (argument marshalling only).
+
+The library must have been built (``python -m paper_1810_08142_amd.build`` or
+``__graft_entry__.build()``); there is no fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libriccsd.so")
+
+_c = ctypes
+_dp = _c.c_void_p  # device pointers travel as plain addresses
+_lib = None
+
+
+class RIError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("ri_status_str", _c.c_char_p, [_c.c_int]),
+    ("ri_last_error_msg", _c.c_char_p, []),
+    ("ri_last_hip_error", _c.c_int, []),
+    ("ri_ppl", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _dp]),
+    ("ri_ppl_ex", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _c.c_int, _dp, _c.c_size_t, _dp]),
+    ("ri_ppl_workspace_bytes", _c.c_size_t, [_c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    ("ri_ppl_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
+    ("ri_build_tau", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _dp, _dp]),
+]
+
+
+def lib():
+    """Load the HIP library (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run `python -m paper_1810_08142_amd.build`)")
+        L = _c.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    return [s[0] for s in _SIGS]
+
+
+def check(status: int, where: str):
+    if status != 0:
+        L = lib()
+        raise RIError(status, where, L.ri_last_error_msg().decode() or L.ri_status_str(status).decode())

@@ -1,0 +1,150 @@
+"""Ladder parity on the GPU: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerance (FP64 path): max|dR| / max|R_ref| <= 1e-11 and ||dR||_F / ||R_ref||_F <= 1e-11
+(the config's "within 1e-11 relative"; element-wise relative error is ill-posed
+near zeros).  Both sides accumulate sums of v^2 * naux products in FP64 in a
+different order; their rounding differs by O(1e-15) relative to the terms."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, rel_fro, rel_max
+from oracle import ccsd as oc
+from oracle import native
+from paper_1810_08142_amd.synthetic import CONFIGS, draw_matrix, draw_pair_symmetric, draw_system
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def _ppl():
+    from paper_1810_08142_amd import ppl
+    return ppl
+
+
+def _gpu_ladder(B_vv, tau, R0=None, precision="fp64"):
+    import torch
+    o, v = tau.shape[0], tau.shape[2]
+    R = dev(R0) if R0 is not None else torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    _ppl().ppl(dev(B_vv), dev(tau), R, precision=precision)
+    return host(R)
+
+
+SHAPES = [  # (o, v, naux): tiny, one tile, ragged tails across several tiles, the CCSD config
+    (1, 3, 2), (1, 16, 16), (2, 17, 7), (3, 33, 20), (4, 24, 96), (5, 40, 37), (2, 50, 130),
+]
+
+
+@pytest.mark.parametrize("o,v,naux", SHAPES)
+def test_parity_small(o, v, naux):
+    print(f"ppl parity o={o} v={v} naux={naux}", flush=True)
+    s = draw_system(o, v, naux, seed=300 + v)
+    tau = draw_pair_symmetric(o, v, 400 + v)
+    R0 = draw_matrix((o, o, v, v), 500 + v)
+    got = _gpu_ladder(s.B_vv, tau, R0)
+    ref = native.ppl(s.B_vv, tau, R0.copy())
+    assert rel_max(got - R0, ref - R0) <= TOL
+    assert rel_fro(got - R0, ref - R0) <= TOL
+
+
+def test_nonsymmetric_factors():
+    # t1-dressed factors are not symmetric in (a, c)
+    o, v, naux = 3, 21, 11
+    s = draw_system(o, v, naux, seed=601, scale=0.2)
+    t1 = draw_matrix((o, v), 602, 0.1)
+    Bd = np.ascontiguousarray(oc.dress(s.B, t1)[:, o:, o:])
+    assert np.abs(Bd - Bd.transpose(0, 2, 1)).max() > 1e-3
+    tau = draw_pair_symmetric(o, v, 603)
+    got = _gpu_ladder(Bd, tau)
+    ref = native.ppl(Bd, tau)
+    assert rel_max(got, ref) <= TOL
+
+
+def test_uses_pair_symmetric_part_of_tau():
+    o, v, naux = 3, 19, 9
+    s = draw_system(o, v, naux, seed=611)
+    x = draw_matrix((o, o, v, v), 612)
+    got = _gpu_ladder(s.B_vv, x)
+    ref = native.ppl(s.B_vv, 0.5 * (x + x.transpose(1, 0, 3, 2)))
+    assert rel_max(got, ref) <= TOL
+
+
+def test_pair_symmetry_bitwise_and_deterministic():
+    o, v, naux = 4, 37, 25
+    s = draw_system(o, v, naux, seed=621)
+    tau = draw_pair_symmetric(o, v, 622)
+    R1 = _gpu_ladder(s.B_vv, tau)
+    R2 = _gpu_ladder(s.B_vv, tau)
+    assert np.array_equal(R1, R2)
+    assert np.array_equal(R1, R1.transpose(1, 0, 3, 2))
+
+
+def test_slabs_do_not_change_result():
+    o, v, naux = 3, 70, 18
+    s = draw_system(o, v, naux, seed=631)
+    tau = draw_pair_symmetric(o, v, 632)
+    R1 = _gpu_ladder(s.B_vv, tau)
+    os.environ["RI_PPL_SLAB_PAIRS"] = "2"
+    try:
+        R2 = _gpu_ladder(s.B_vv, tau)
+    finally:
+        del os.environ["RI_PPL_SLAB_PAIRS"]
+    assert np.array_equal(R1, R2)
+
+
+def test_caller_workspace_and_errors():
+    import torch
+    from paper_1810_08142_amd import _lib
+    ppl = _ppl()
+    o, v, naux = 2, 20, 8
+    s = draw_system(o, v, naux, seed=641)
+    tau = draw_pair_symmetric(o, v, 642)
+    nbytes = ppl.workspace_bytes(o, v, naux)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    R = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    ppl.ppl(dev(s.B_vv), dev(tau), R, workspace=ws)
+    assert rel_max(host(R), native.ppl(s.B_vv, tau)) <= TOL
+    small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(_lib.RIError) as e:
+        ppl.ppl(dev(s.B_vv), dev(tau), R, workspace=small)
+    assert e.value.status == 3
+    T = dev(tau)
+    with pytest.raises(_lib.RIError) as e:
+        ppl.ppl(dev(s.B_vv), T, T)  # R aliases tau
+    assert e.value.status == 2
+
+
+def test_build_tau():
+    o, v = 3, 11
+    t1 = draw_matrix((o, v), 651, 0.1)
+    t2 = draw_pair_symmetric(o, v, 652)
+    got = host(_ppl().build_tau(dev(t1), dev(t2)))
+    ref = oc.make_tau(t1, t2)
+    # one rounding of a fused multiply-add vs two roundings on the host
+    bound = 2.0 * np.finfo(np.float64).eps * (np.abs(t2) + np.abs(np.einsum("ia,jb->ijab", t1, t1)))
+    assert bool(np.all(np.abs(got - ref) <= bound))
+
+
+def test_c2_full_size_sampled():
+    """c2 (o=16, v=256, naux=768) in the benchmark's launch configuration; tau is the
+    oracle's MP2 t2 + t1 (x) t1.  The oracle recomputes 48 sampled (a, b) pairs."""
+    import torch
+    c = CONFIGS["c2"]
+    o, v, naux = c["o"], c["v"], c["naux"]
+    print("c2: drawing system", flush=True)
+    s = draw_system(o, v, naux, seed=c["seed"])
+    _, t2, _ = oc.mp2(s.B, s.eps, o)
+    tau = oc.make_tau(s.t1, t2)
+    B_vv = s.B_vv
+    print("c2: GPU ladder", flush=True)
+    R = _gpu_ladder(B_vv, tau)
+    rng = np.random.default_rng(7)
+    pairs = [(int(a), int(b)) for a, b in rng.integers(0, v, size=(44, 2))] + [(0, 0), (v - 1, v - 1), (0, v - 1), (v - 1, 0)]
+    print("c2: oracle sample", flush=True)
+    ref = native.ppl_pairs(B_vv, tau, pairs)
+    got = np.stack([R[:, :, a, b] for a, b in pairs])
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() / scale <= TOL
+    assert np.array_equal(R, R.transpose(1, 0, 3, 2))
+    assert np.isfinite(R).all()
