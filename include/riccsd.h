@@ -85,9 +85,79 @@ size_t ri_ppl_workspace_bytes(int o, int v, int naux, int precision);
  * multiply-add counts two).  0 on invalid arguments. */
 double ri_ppl_flops(int o, int v, int naux);
 
+/* Per-kernel timing.  While enabled, the library brackets each of its kernel
+ * launches with HIP events on the launch stream.  ri_prof_report synchronises
+ * those events, writes a JSON array [{"name", "count", "ms", "flops", "bytes"}]
+ * (summed per kernel name; flops/bytes are the algorithmic counts of the work
+ * launched) into buf, and clears the records.  RI_E_ARG if buf is too small. */
+int ri_prof_enable(int on);
+int ri_prof_report(char* buf, size_t len);
+
 /* tau[i][j][a][b] = t2[i][j][a][b] + t1[i][a] t1[j][b]   (eq. pp-Ladder-01).
  * t1: [o][v], t2 and tau: [o][o][v][v]; tau may alias t2 (in place). */
 int ri_build_tau(const double* t1, const double* t2, int o, int v, double* tau, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Closed-shell RI-CCSD (Sec. II.A: eqs. ccsd-1..3 solved by Jacobi iterations
+ * with DIIS; energy expression of Sec. II.A).  Canonical Hartree-Fock orbitals
+ * are assumed: the Fock matrix is diag(eps), and the bare one-electron matrix is
+ * derived from it as h = diag(eps) - sum_k [2 (pq|kk) - (pk|kq)].
+ * ------------------------------------------------------------------------ */
+typedef struct ri_system {
+  int o, v, naux;
+  const double* B;   /* [naux][n][n], n = o + v, RI factors symmetric in the MO pair */
+  const double* eps; /* [n] orbital energies, occupied first */
+} ri_system;
+
+#define RI_GUESS_MP2 0  /* t1 = 0, t2 = (ia|jb) / D (iteration 0) */
+#define RI_GUESS_USER 1 /* start from the t1, t2 passed in */
+
+typedef struct ri_ccsd_opts {
+  int max_iter;        /* iteration limit (default 100) */
+  double tol_residual; /* converged when max |Omega| <= tol_residual ... (default 1e-10) */
+  double tol_energy;   /* ... and |E_k - E_{k-1}| <= tol_energy (default 1e-10) */
+  int diis_size;       /* stored vectors, 2..16; < 2 disables DIIS (default 6) */
+  int diis_start;      /* first iteration that extrapolates (default 2) */
+  int ppl_precision;   /* RI_PREC_* of the ladder term (default RI_PREC_FP64) */
+  int guess;           /* RI_GUESS_MP2 or RI_GUESS_USER */
+  int verbose;         /* one line per iteration on stderr */
+} ri_ccsd_opts;
+
+typedef struct ri_ccsd_report {
+  double e_corr;       /* correlation energy of the returned amplitudes (Hartree) */
+  double e_mp2;        /* MP2 energy of the guess (NaN for RI_GUESS_USER) */
+  double residual_inf; /* max |Omega| at the last residual evaluation */
+  int iterations;      /* residual evaluations minus one */
+  int converged;
+  double seconds_total; /* wall time of the call, guess included */
+  double seconds_ppl;   /* GPU time of the ladder term */
+} ri_ccsd_report;
+
+/* Fills the defaults listed above. */
+void ri_ccsd_default_opts(ri_ccsd_opts* opts);
+
+/* t1 = 0 ([o][v]); t2[i][j][a][b] = (ia|jb) / (e_i + e_j - e_a - e_b); optional MP2
+ * energy on the host (synchronises stream when e_mp2 != NULL). */
+int ri_mp2_guess(const ri_system* sys, double* t1, double* t2, double* e_mp2, void* stream);
+
+/* E_corr = sum_ijab (2 (ia|jb) - (ib|ja)) (t2[i][j][a][b] + t1[i][a] t1[j][b]), reduced in
+ * FP64 in a fixed order; written to the host (synchronises stream). */
+int ri_ccsd_energy(const ri_system* sys, const double* t1, const double* t2, double* e_corr, void* stream);
+
+/* CCSD residuals for the given amplitudes: omega1 [o][v], omega2 [o][o][v][v]
+ * (projections of eqs. ccsd-2/-3 in the biorthogonal basis; at t = 0 omega2 is
+ * (ia|jb) and omega1 is 0).  The ladder term uses ppl_precision.  Outputs must
+ * not overlap the amplitudes. */
+int ri_ccsd_residual(const ri_system* sys, const double* t1, const double* t2, double* omega1, double* omega2,
+                     int ppl_precision, void* stream);
+
+/* Iterate t += Omega / D with DIIS from the chosen guess until converged or
+ * opts->max_iter residual evaluations.  t1, t2 are overwritten with the final
+ * amplitudes (t2 kept pair-symmetric).  Returns RI_E_NOCONV (amplitudes valid)
+ * when the limit is reached, RI_E_NUMERIC on NaN/Inf or divergence.  `rep` may
+ * be NULL.  opts == NULL uses the defaults.  Synchronises stream. */
+int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_opts* opts,
+                    ri_ccsd_report* rep, void* stream);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,25 @@ class RIError(RuntimeError):
         self.status = status
 
 
+class RISystem(_c.Structure):
+    _fields_ = [("o", _c.c_int), ("v", _c.c_int), ("naux", _c.c_int), ("B", _dp), ("eps", _dp)]
+
+
+class RICcsdOpts(_c.Structure):
+    _fields_ = [("max_iter", _c.c_int), ("tol_residual", _c.c_double), ("tol_energy", _c.c_double),
+                ("diis_size", _c.c_int), ("diis_start", _c.c_int), ("ppl_precision", _c.c_int),
+                ("guess", _c.c_int), ("verbose", _c.c_int)]
+
+
+class RICcsdReport(_c.Structure):
+    _fields_ = [("e_corr", _c.c_double), ("e_mp2", _c.c_double), ("residual_inf", _c.c_double),
+                ("iterations", _c.c_int), ("converged", _c.c_int), ("seconds_total", _c.c_double),
+                ("seconds_ppl", _c.c_double)]
+
+
+_sysp = _c.POINTER(RISystem)
+_dblp = _c.POINTER(_c.c_double)
+
 # (name, restype, argtypes)
 _SIGS = [
     ("ri_status_str", _c.c_char_p, [_c.c_int]),
@@ -32,6 +51,13 @@ _SIGS = [
     ("ri_ppl_workspace_bytes", _c.c_size_t, [_c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_build_tau", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _dp, _dp]),
+    ("ri_prof_enable", _c.c_int, [_c.c_int]),
+    ("ri_prof_report", _c.c_int, [_c.c_char_p, _c.c_size_t]),
+    ("ri_ccsd_default_opts", None, [_c.POINTER(RICcsdOpts)]),
+    ("ri_mp2_guess", _c.c_int, [_sysp, _dp, _dp, _dblp, _dp]),
+    ("ri_ccsd_energy", _c.c_int, [_sysp, _dp, _dp, _dblp, _dp]),
+    ("ri_ccsd_residual", _c.c_int, [_sysp, _dp, _dp, _dp, _dp, _c.c_int, _dp]),
+    ("ri_ccsd_iterate", _c.c_int, [_sysp, _dp, _dp, _c.POINTER(RICcsdOpts), _c.POINTER(RICcsdReport), _dp]),
 ]
 
 
@@ -59,3 +85,15 @@ def check(status: int, where: str):
     if status != 0:
         L = lib()
         raise RIError(status, where, L.ri_last_error_msg().decode() or L.ri_status_str(status).decode())
+
+
+def prof_enable(on: bool = True):
+    lib().ri_prof_enable(1 if on else 0)
+
+
+def prof_report() -> list:
+    """Per-kernel event timings recorded since the last report (synchronises)."""
+    import json
+    buf = _c.create_string_buffer(1 << 16)
+    check(lib().ri_prof_report(buf, len(buf)), "ri_prof_report")
+    return json.loads(buf.value.decode())

@@ -1,5 +1,6 @@
 // Status strings, per-thread error state and stream-ordered workspace helpers.
 #include <cstdarg>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -67,9 +68,102 @@ void dev_free(void* p, hipStream_t s) {
   if (p) (void)hipFreeAsync(p, s);
 }
 
+// ------------------------------------------------------------------ profiling
+namespace {
+struct ProfRec {
+  std::string name;
+  hipEvent_t start, stop;
+  double flops, bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+}  // namespace
+
+ProfScope::ProfScope(hipStream_t s, const char* name, double flops, double bytes) : s_(s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return;
+  ProfRec r{name, nullptr, nullptr, flops, bytes};
+  if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (hipEventRecord(r.start, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  idx_ = static_cast<int>(g_prof.size());
+  g_prof.push_back(r);
+}
+
+ProfScope::~ProfScope() {
+  if (idx_ < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (idx_ < static_cast<int>(g_prof.size())) (void)hipEventRecord(g_prof[idx_].stop, s_);
+}
+
 }  // namespace ri
 
 extern "C" {
+
+int ri_prof_enable(int on) {
+  std::lock_guard<std::mutex> lk(ri::g_prof_mu);
+  ri::g_prof_on = on != 0;
+  return RI_OK;
+}
+
+int ri_prof_report(char* buf, size_t len) {
+  ri::clear_error();
+  if (!buf || len == 0) {
+    ri::set_error("ri_prof_report: null buffer");
+    return RI_E_ARG;
+  }
+  std::vector<ri::ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(ri::g_prof_mu);
+    recs.swap(ri::g_prof);
+  }
+  struct Agg {
+    std::string name;
+    int count = 0;
+    double ms = 0, flops = 0, bytes = 0;
+  };
+  std::vector<Agg> agg;
+  int rc = RI_OK;
+  for (auto& r : recs) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+    if (e != hipSuccess) rc = ri::check_hip(e, "ri_prof_report");
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+    Agg* a = nullptr;
+    for (auto& x : agg)
+      if (x.name == r.name) a = &x;
+    if (!a) {
+      agg.push_back(Agg{r.name});
+      a = &agg.back();
+    }
+    a->count += 1;
+    a->ms += ms;
+    a->flops += r.flops;
+    a->bytes += r.bytes;
+  }
+  std::string out = "[";
+  for (size_t k = 0; k < agg.size(); ++k) {
+    char line[256];
+    snprintf(line, sizeof(line), "%s{\"name\": \"%s\", \"count\": %d, \"ms\": %.6f, \"flops\": %.6e, \"bytes\": %.6e}",
+             k ? ", " : "", agg[k].name.c_str(), agg[k].count, agg[k].ms, agg[k].flops, agg[k].bytes);
+    out += line;
+  }
+  out += "]";
+  if (out.size() + 1 > len) {
+    ri::set_error("ri_prof_report: buffer of %zu bytes too small (%zu needed)", len, out.size() + 1);
+    return RI_E_ARG;
+  }
+  memcpy(buf, out.c_str(), out.size() + 1);
+  return rc;
+}
 
 const char* ri_status_str(int status) {
   switch (status) {

@@ -29,6 +29,7 @@
 //      build      W+-[cd slot][ab slot] = (ac|bd) +- (ad|bc)  (MFMA over Q, B staged in LDS)
 //      contract   S = W+^T T+, A = W-^T T-                    (MFMA over cd slots)
 //      unpack     R += mirrored S +- A                         (LDS transposes, coalesced)
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 
@@ -59,14 +60,14 @@ __device__ inline double4_t mfma_f64(double a, double b, double4_t c) {
 }
 
 // ---------------------------------------------------------------- 1. relayout
-// grid (naux_p, vp/16, vp/16), block 256
-__global__ __launch_bounds__(256) void relayout_b_f64(const double* __restrict__ B, int v, int naux,
-                                                      int vp, int naux_p, double* __restrict__ Bc) {
+// B[q][a][c] lives at B + q*qs + a*rs + c.  grid (naux_p, vp/16, vp/16), block 256
+__global__ __launch_bounds__(256) void relayout_b_f64(const double* __restrict__ B, long qs, long rs, int v,
+                                                      int naux, int vp, int naux_p, double* __restrict__ Bc) {
   __shared__ double tile[TB][TB + 1];
   const int q = blockIdx.x, a0 = blockIdx.y * TB, c0 = blockIdx.z * TB;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int a = a0 + ty, c = c0 + tx;
-  tile[ty][tx] = (a < v && c < v && q < naux) ? B[(static_cast<size_t>(q) * v + a) * v + c] : 0.0;
+  tile[ty][tx] = (a < v && c < v && q < naux) ? B[q * qs + a * rs + c] : 0.0;
   __syncthreads();
   Bc[(static_cast<size_t>(c0 + ty) * naux_p + q) * vp + a0 + tx] = tile[tx][ty];
 }
@@ -460,8 +461,25 @@ static void launch_contract(int ntw, const double* W, const double* T, long K, l
   }
 }
 
-static int run_f64(const Plan& p, const double* B_vv, const double* tau, double* R, void* ws,
-                   hipStream_t s) {
+// Valid (a <= b) and (a < b) virtual pairs inside block pairs [p0, p0 + n).
+static void count_pairs(const Plan& p, long p0, long n, double& le, double& lt) {
+  le = lt = 0;
+  for (long q = p0; q < p0 + n; ++q) {
+    int X, Y;
+    tri_decode(q, X, Y);
+    const double nx = std::min(TB, p.v - X * TB), ny = std::min(TB, p.v - Y * TB);
+    if (X < Y) {
+      le += nx * ny;
+      lt += nx * ny;
+    } else {
+      le += nx * (nx + 1) / 2;
+      lt += nx * (nx - 1) / 2;
+    }
+  }
+}
+
+static int run_f64(const Plan& p, const double* B_vv, long qs, long rs, const double* tau, double* R,
+                   void* ws, hipStream_t s) {
   Carve cv(ws, p.bytes);
   double* Bc = cv.take<double>(p.n_Bc);
   double* Tp = cv.take<double>(p.n_Tp);
@@ -471,33 +489,72 @@ static int run_f64(const Plan& p, const double* B_vv, const double* tau, double*
   double* S = cv.take<double>(p.n_S);
   double* A = cv.take<double>(p.n_A);
 
-  relayout_b_f64<<<dim3(p.naux_p, p.nb, p.nb), 256, 0, s>>>(B_vv, p.v, p.naux, p.vp, p.naux_p, Bc);
-  RI_TRY(check_launch("relayout_b_f64"));
-  pack_tau_f64<<<dim3(p.nbp, p.NP / NG), 256, 0, s>>>(tau, p.o, p.v, p.NP, +1, Tp);
-  RI_TRY(check_launch("pack_tau_f64(+)"));
-  if (p.pm > 0) {
-    pack_tau_f64<<<dim3(p.nbp, p.NM / NG), 256, 0, s>>>(tau, p.o, p.v, p.NM, -1, Tm);
-    RI_TRY(check_launch("pack_tau_f64(-)"));
+  const double vv = static_cast<double>(p.v) * p.v, oo = static_cast<double>(p.o) * p.o;
+  const double pv = p.v * (p.v + 1.0) / 2, pvm = p.v * (p.v - 1.0) / 2;
+  {
+    ProfScope ps(s, "relayout_b_f64", 0.0, 8.0 * vv * p.naux * 2);
+    relayout_b_f64<<<dim3(p.naux_p, p.nb, p.nb), 256, 0, s>>>(B_vv, qs, rs, p.v, p.naux, p.vp, p.naux_p, Bc);
+    RI_TRY(check_launch("relayout_b_f64"));
+  }
+  {
+    ProfScope ps(s, "pack_tau_f64", 0.0, 8.0 * (oo * vv + pv * p.po + pvm * p.pm));
+    pack_tau_f64<<<dim3(p.nbp, p.NP / NG), 256, 0, s>>>(tau, p.o, p.v, p.NP, +1, Tp);
+    RI_TRY(check_launch("pack_tau_f64(+)"));
+    if (p.pm > 0) {
+      pack_tau_f64<<<dim3(p.nbp, p.NM / NG), 256, 0, s>>>(tau, p.o, p.v, p.NM, -1, Tm);
+      RI_TRY(check_launch("pack_tau_f64(-)"));
+    }
   }
   for (long slab0 = 0; slab0 < p.nbp; slab0 += p.slab_bp) {
     const long npairs = (p.nbp - slab0) < p.slab_bp ? (p.nbp - slab0) : p.slab_bp;
     const long M = npairs * 256;
-    build_w_f64<<<dim3(p.nbp * 4, npairs), 512, 0, s>>>(Bc, p.naux_p, p.vp, slab0, p.slab_M,
-                                                        p.pm > 0 ? 1 : 0, Wp, Wm);
-    RI_TRY(check_launch("build_w_f64"));
-    launch_contract(p.ntw_p, Wp, Tp, p.K, p.slab_M, M, p.NP, S, s);
-    RI_TRY(check_launch("contract_f64(+)"));
-    if (p.pm > 0) {
-      launch_contract(p.ntw_m, Wm, Tm, p.K, p.slab_M, M, p.NM, A, s);
-      RI_TRY(check_launch("contract_f64(-)"));
+    double le, lt;
+    count_pairs(p, slab0, npairs, le, lt);
+    {
+      // per valid (a <= b): the v x v matrix (ac|bd) over all c, d, naux products each
+      ProfScope ps(s, "build_w_f64", 2.0 * p.naux * vv * le);
+      build_w_f64<<<dim3(p.nbp * 4, npairs), 512, 0, s>>>(Bc, p.naux_p, p.vp, slab0, p.slab_M,
+                                                          p.pm > 0 ? 1 : 0, Wp, Wm);
+      RI_TRY(check_launch("build_w_f64"));
     }
-    unpack_f64<<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R);
-    RI_TRY(check_launch("unpack_f64"));
+    {
+      ProfScope ps(s, "contract_f64", 2.0 * (le * pv * p.po + lt * pvm * p.pm));
+      launch_contract(p.ntw_p, Wp, Tp, p.K, p.slab_M, M, p.NP, S, s);
+      RI_TRY(check_launch("contract_f64(+)"));
+      if (p.pm > 0) {
+        launch_contract(p.ntw_m, Wm, Tm, p.K, p.slab_M, M, p.NM, A, s);
+        RI_TRY(check_launch("contract_f64(-)"));
+      }
+    }
+    {
+      ProfScope ps(s, "unpack_f64", 0.0, 16.0 * oo * (le + lt));
+      unpack_f64<<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R);
+      RI_TRY(check_launch("unpack_f64"));
+    }
   }
   return RI_OK;
 }
 
 }  // namespace ppl
+
+int ppl_strided(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
+                int precision, hipStream_t s) {
+  ppl::Plan p;
+  if (!ppl::make_plan(o, v, naux, p)) {
+    set_error("ladder: invalid sizes o=%d v=%d naux=%d", o, v, naux);
+    return RI_E_ARG;
+  }
+  if (precision != RI_PREC_FP64) {
+    set_error("ladder: precision %d not available in this build", precision);
+    return RI_E_UNSUPPORTED;
+  }
+  void* buf = nullptr;
+  RI_TRY(dev_alloc(&buf, p.bytes, s));
+  const int rc = ppl::run_f64(p, B, qs, rs, tau, R, buf, s);
+  dev_free(buf, s);
+  return rc;
+}
+
 }  // namespace ri
 
 using namespace ri;
@@ -565,7 +622,7 @@ int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, dou
     RI_TRY(dev_alloc(&buf, p.bytes, s));
     own = true;
   }
-  int rc = ppl::run_f64(p, B_vv, tau, R, buf, s);
+  int rc = ppl::run_f64(p, B_vv, static_cast<long>(v) * v, v, tau, R, buf, s);
   if (own) dev_free(buf, s);
   return rc;
 }

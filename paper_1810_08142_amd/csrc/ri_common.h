@@ -36,6 +36,25 @@ inline int check_hip(hipError_t e, const char* where) {
 int dev_alloc(void** p, size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
 
+// Per-kernel timing: when enabled (ri_prof_enable), a ProfScope records HIP events
+// around the launches it encloses on stream `s`; ri_prof_report sums them by name.
+class ProfScope {
+ public:
+  ProfScope(hipStream_t s, const char* name, double flops, double bytes = 0.0);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  hipStream_t s_;
+  int idx_ = -1;
+};
+
+// Ladder on factors stored with strides: B[q][a][c] at B + q*qs + a*rs + c
+// (R += sum_cd (ac|bd) tau^{cd}_{ij}; workspace allocated on stream s).
+int ppl_strided(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
+                int precision, hipStream_t s);
+
 // Byte ranges [a, a+na) and [b, b+nb) overlap?
 inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
