@@ -8,6 +8,7 @@ from __future__ import annotations
 import concurrent.futures as cf
 import glob
 import os
+import re
 import subprocess
 import sys
 
@@ -26,12 +27,30 @@ FLAGS = [
 ]
 
 
+def _scratch_users(remarks: str):
+    """Kernels whose resource-usage remark reports private (scratch) memory."""
+    bad, name = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and int(m.group(1)) > 0 and name:
+            bad.append((name, int(m.group(1))))
+    return bad
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+    cmd = ["hipcc", *FLAGS, "-Rpass-analysis=kernel-resource-usage", "-I", os.path.join(ROOT, "include"),
+           "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    # a kernel spilling its staging registers to scratch loses its latency hiding
+    bad = _scratch_users(r.stderr)
+    if bad:
+        raise RuntimeError(f"{os.path.basename(src)}: kernels use scratch memory: {bad}")
     return obj
 
 

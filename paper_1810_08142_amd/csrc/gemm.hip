@@ -74,22 +74,6 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, const long* _
   const long boff = brow ? bnoff[bn + bnn] : 0;
 
   double ra[4], rb[4];
-  auto gload = [&](long k0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long ka = k0 + ak + r * akstep, kb = k0 + bk + r * bkstep;
-      ra[r] = (arow && ka < g.K) ? A[aoff + akoff[ka]] : 0.0;
-      rb[r] = (brow && kb < g.K) ? B[boff + bkoff[kb]] : 0.0;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      sA[buf][ak + r * akstep][am] = ra[r];
-      sB[buf][bk + r * bkstep][bnn] = rb[r];
-    }
-  };
-
   double4_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -98,12 +82,30 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, const long* _
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
   const int l16 = lane & 15, kq = lane >> 4;
   const long nchunks = (g.K + KC - 1) / KC;
-  gload(0);
-  sstore(0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const long ka = ak + r * akstep, kb = bk + r * bkstep;
+    ra[r] = (arow && ka < g.K) ? A[aoff + akoff[ka]] : 0.0;
+    rb[r] = (brow && kb < g.K) ? B[boff + bkoff[kb]] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    sA[0][ak + r * akstep][am] = ra[r];
+    sB[0][bk + r * bkstep][bnn] = rb[r];
+  }
   __syncthreads();
   for (long ch = 0; ch < nchunks; ++ch) {
     const int buf = ch & 1;
-    if (ch + 1 < nchunks) gload((ch + 1) * KC);
+    const bool more = ch + 1 < nchunks;
+    if (more) {
+      const long k0 = (ch + 1) * KC;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long ka = k0 + ak + r * akstep, kb = k0 + bk + r * bkstep;
+        ra[r] = (arow && ka < g.K) ? A[aoff + akoff[ka]] : 0.0;
+        rb[r] = (brow && kb < g.K) ? B[boff + bkoff[kb]] : 0.0;
+      }
+    }
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int kk = 4 * s + kq;
@@ -117,7 +119,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, const long* _
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (ch + 1 < nchunks) sstore(buf ^ 1);
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        sA[buf ^ 1][ak + r * akstep][am] = ra[r];
+        sB[buf ^ 1][bk + r * bkstep][bnn] = rb[r];
+      }
+    }
     __syncthreads();
   }
   // D[4r + lane/16][lane%16] in element r

@@ -43,6 +43,7 @@ constexpr int KC = 16;  // auxiliary functions staged per LDS step
 constexpr int NG = 16;  // column granule of the packed amplitudes
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));  // register-promotable (unlike double2)
 
 __host__ __device__ inline void tri_decode(long p, int& x, int& y) {
   // p = y(y+1)/2 + x with 0 <= x <= y
@@ -134,30 +135,22 @@ __global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc
   const int d_base = Db * TB + (quarter & 1) * 8;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 
-  // global -> register staging: 8 double2 per thread per chunk
-  const double* src[8];
+  // global -> register -> LDS staging: 8 double2 per thread per chunk.  Offsets are
+  // computed once; the chunk loop only adds the Q stride.
+  size_t goff[8];
+  int loff[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int p2 = t + 512 * r;  // [0, 4096)
     const int x = p2 >> 8, k = (p2 >> 4) & 15, e = (p2 & 15) * 2;
     const int cg = x < 8 ? c_base + x : d_base + (x - 8);
     const int ag = e < 16 ? Ab * TB + e : Bb * TB + (e - 16);
-    src[r] = Bc + (static_cast<size_t>(cg) * naux_p + k) * vp + ag;
+    goff[r] = (static_cast<size_t>(cg) * naux_p + k) * vp + ag;
+    loff[r] = (x * KC + k) * 32 + e;
   }
   const size_t qstride = static_cast<size_t>(vp) * KC;  // advance one chunk of Q
-  double2 stage[8];
-  auto gload = [&](int chunk) {
-#pragma unroll
-    for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const double2*>(src[r] + chunk * qstride);
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int p2 = t + 512 * r;
-      const int x = p2 >> 8, k = (p2 >> 4) & 15, e = (p2 & 15) * 2;
-      *reinterpret_cast<double2*>(&lds[buf][x][k][e]) = stage[r];
-    }
-  };
+  double* lds0 = &lds[0][0][0][0];
+  constexpr int LBUF = 16 * KC * 32;
 
   double4_t acc1[2][4], acc2[2][4];
 #pragma unroll
@@ -171,12 +164,20 @@ __global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc
   const int xc0 = (w >> 1) * 2, xd0 = 8 + (w & 1) * 4;
   const int m = lane & 15, kq = lane >> 4;
   const int nchunks = naux_p / KC;
-  gload(0);
-  sstore(0);
+  double2_t stage[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const double2_t*>(Bc + goff[r]);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) *reinterpret_cast<double2_t*>(lds0 + loff[r]) = stage[r];
   __syncthreads();
   for (int ch = 0; ch < nchunks; ++ch) {
     const int buf = ch & 1;
-    if (ch + 1 < nchunks) gload(ch + 1);
+    const bool more = ch + 1 < nchunks;
+    if (more) {
+      const size_t qo = static_cast<size_t>(ch + 1) * qstride;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const double2_t*>(Bc + goff[r] + qo);
+    }
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int kk = 4 * s + kq;
@@ -199,7 +200,11 @@ __global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc
           acc2[i][j] = mfma_f64(a_d[j], b_c[i], acc2[i][j]);  // (ad|bc)
         }
     }
-    if (ch + 1 < nchunks) sstore(buf ^ 1);
+    if (more) {
+      double* dst = lds0 + (buf ^ 1) * LBUF;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) *reinterpret_cast<double2_t*>(dst + loff[r]) = stage[r];
+    }
     __syncthreads();
   }
 
@@ -236,47 +241,52 @@ __global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W
   const long n0 = static_cast<long>(blockIdx.x) * BN, m0 = static_cast<long>(blockIdx.y) * 64;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 
-  double2 ra[2];
+  // staging offsets (computed once; the chunk loop adds k0 * row stride)
+  long aoff[2], boff[NTW];
+  int alo[2], blo[NTW];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int p2 = t + 256 * r;
+    const int k = p2 >> 5, mm = (p2 & 31) * 2;
+    aoff[r] = k * M + m0 + mm;
+    alo[r] = k * 64 + mm;
+  }
+#pragma unroll
+  for (int r = 0; r < NTW; ++r) {
+    const int e = t + 256 * r;
+    const int k = e / BN, nn = e % BN;
+    boff[r] = static_cast<long>(k) * ncol + n0 + nn;
+    blo[r] = k * BN + nn;
+  }
+  double2_t ra[2];
   double rb[NTW];
-  auto gload = [&](long k0) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int p2 = t + 256 * r;
-      const int k = p2 >> 5, mm = (p2 & 31) * 2;
-      ra[r] = *reinterpret_cast<const double2*>(W + (k0 + k) * M + m0 + mm);
-    }
-#pragma unroll
-    for (int r = 0; r < NTW; ++r) {
-      const int e = t + 256 * r;
-      const int k = e / BN, nn = e % BN;
-      rb[r] = T[(k0 + k) * ncol + n0 + nn];
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int p2 = t + 256 * r;
-      const int k = p2 >> 5, mm = (p2 & 31) * 2;
-      *reinterpret_cast<double2*>(&sA[buf][k][mm]) = ra[r];
-    }
-#pragma unroll
-    for (int r = 0; r < NTW; ++r) {
-      const int e = t + 256 * r;
-      sB[buf][e / BN][e % BN] = rb[r];
-    }
-  };
+  double* sA0 = &sA[0][0][0];
+  double* sB0 = &sB[0][0][0];
 
   double4_t acc[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) acc[u] = double4_t{0.0, 0.0, 0.0, 0.0};
   const int m = lane & 15, kq = lane >> 4;
   const long nchunks = K / KC;
-  gload(0);
-  sstore(0);
+#pragma unroll
+  for (int r = 0; r < 2; ++r) ra[r] = *reinterpret_cast<const double2_t*>(W + aoff[r]);
+#pragma unroll
+  for (int r = 0; r < NTW; ++r) rb[r] = T[boff[r]];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) *reinterpret_cast<double2_t*>(sA0 + alo[r]) = ra[r];
+#pragma unroll
+  for (int r = 0; r < NTW; ++r) sB0[blo[r]] = rb[r];
   __syncthreads();
   for (long ch = 0; ch < nchunks; ++ch) {
     const int buf = ch & 1;
-    if (ch + 1 < nchunks) gload((ch + 1) * KC);
+    const bool more = ch + 1 < nchunks;
+    if (more) {
+      const long k0 = (ch + 1) * KC;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) ra[r] = *reinterpret_cast<const double2_t*>(W + aoff[r] + k0 * M);
+#pragma unroll
+      for (int r = 0; r < NTW; ++r) rb[r] = T[boff[r] + k0 * ncol];
+    }
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int kk = 4 * s + kq;
@@ -284,7 +294,12 @@ __global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W
 #pragma unroll
       for (int u = 0; u < NTW; ++u) acc[u] = mfma_f64(a, sB[buf][kk][u * 16 + m], acc[u]);
     }
-    if (ch + 1 < nchunks) sstore(buf ^ 1);
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) *reinterpret_cast<double2_t*>(sA0 + (buf ^ 1) * KC * 64 + alo[r]) = ra[r];
+#pragma unroll
+      for (int r = 0; r < NTW; ++r) sB0[(buf ^ 1) * KC * BN + blo[r]] = rb[r];
+    }
     __syncthreads();
   }
 #pragma unroll
