@@ -33,26 +33,15 @@
 #include <cmath>
 #include <cstdlib>
 
-#include "ri_common.h"
+#include "ppl_shared.h"
 
 namespace ri {
 namespace ppl {
 
-constexpr int TB = 16;  // virtual block size
-constexpr int KC = 16;  // auxiliary functions staged per LDS step
-constexpr int NG = 16;  // column granule of the packed amplitudes
+constexpr int KC = 16;  // auxiliary functions staged per LDS step (FP64 path)
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef double double2_t __attribute__((ext_vector_type(2)));  // register-promotable (unlike double2)
-
-__host__ __device__ inline void tri_decode(long p, int& x, int& y) {
-  // p = y(y+1)/2 + x with 0 <= x <= y
-  long yy = static_cast<long>((sqrt(8.0 * static_cast<double>(p) + 1.0) - 1.0) * 0.5);
-  while ((yy + 1) * (yy + 2) / 2 <= p) ++yy;
-  while (yy * (yy + 1) / 2 > p) --yy;
-  y = static_cast<int>(yy);
-  x = static_cast<int>(p - yy * (yy + 1) / 2);
-}
 
 // D += A B on a 16x16x4 FP64 tile: lane l supplies A[l%16][l/16] and B[l/16][l%16]
 // and holds D[4r + l/16][l%16] in element r.
@@ -312,10 +301,12 @@ __global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W
 }
 
 // ---------------------------------------------------------------- 3c. unpack
+// S and A are FP64 (FP64 path) or FP32 (mixed paths); R accumulates in FP64.
 // grid (slab_pairs, ceil(po/16)), block 256
-__global__ __launch_bounds__(256) void unpack_f64(const double* __restrict__ S, const double* __restrict__ A,
-                                                  int NP, int NM, int o, int v, long slab0,
-                                                  double* __restrict__ R) {
+template <class T>
+__global__ __launch_bounds__(256) void unpack_kernel(const T* __restrict__ S, const T* __restrict__ A,
+                                                     int NP, int NM, int o, int v, long slab0,
+                                                     double* __restrict__ R) {
   __shared__ double sS[256][NG + 1];
   __shared__ double sA[256][NG + 1];
   int Ab, Bb;
@@ -330,8 +321,8 @@ __global__ __launch_bounds__(256) void unpack_f64(const double* __restrict__ S, 
     if (lam < po) {
       int i, j;
       tri_decode(lam, i, j);
-      s = S[(row0 + slot) * NP + lam];
-      if (i < j) x = A[(row0 + slot) * NM + j * (j - 1) / 2 + i];
+      s = static_cast<double>(S[(row0 + slot) * NP + lam]);
+      if (i < j) x = static_cast<double>(A[(row0 + slot) * NM + j * (j - 1) / 2 + i]);
     }
     sS[slot][cc] = s;
     sA[slot][cc] = x;
@@ -366,6 +357,11 @@ __global__ __launch_bounds__(256) void unpack_f64(const double* __restrict__ S, 
   }
 }
 
+void launch_unpack_f32(const float* S, const float* A, int NP, int NM, int o, int v, long slab0, long npairs,
+                       double* R, hipStream_t s) {
+  unpack_kernel<float><<<dim3(npairs, (o * (o + 1) / 2 + NG - 1) / NG), 256, 0, s>>>(S, A, NP, NM, o, v, slab0, R);
+}
+
 // ---------------------------------------------------------------- tau
 __global__ void build_tau_kernel(const double* __restrict__ t1, const double* t2, int o, int v,
                                  double* tau, size_t total) {
@@ -389,31 +385,6 @@ struct Plan {
   size_t bytes;
 };
 
-static void pick_ntw(int ncols, int& ntw, int& padded) {
-  const int n16 = (ncols + NG - 1) / NG;
-  ntw = 1;
-  padded = n16 > 0 ? n16 : 1;
-  int best = 1 << 30;
-  for (int c = 1; c <= 10; ++c) {
-    const int tiles = (n16 + c - 1) / c;
-    const int p = tiles * c;
-    if (p < best || (p == best && c > ntw)) {
-      best = p;
-      ntw = c;
-    }
-  }
-  if (n16 == 0) ntw = 1, best = 1;
-  padded = best * NG;
-}
-
-static long env_long(const char* name, long dflt) {
-  const char* s = getenv(name);
-  if (!s || !*s) return dflt;
-  char* end = nullptr;
-  long x = strtol(s, &end, 10);
-  return (end && *end == 0 && x > 0) ? x : dflt;
-}
-
 static bool make_plan(int o, int v, int naux, Plan& p) {
   if (o <= 0 || v <= 0 || naux <= 0) return false;
   if (o > 4096 || v > 65536 || naux > (1 << 24)) return false;
@@ -427,8 +398,8 @@ static bool make_plan(int o, int v, int naux, Plan& p) {
   p.K = p.nbp * 256;
   p.po = o * (o + 1) / 2;
   p.pm = o * (o - 1) / 2;
-  pick_ntw(p.po, p.ntw_p, p.NP);
-  pick_ntw(p.pm, p.ntw_m, p.NM);
+  pick_ntw(p.po, 10, p.ntw_p, p.NP);
+  pick_ntw(p.pm, 10, p.ntw_m, p.NM);
   if (p.pm == 0) p.NM = 0;
   const int nw = p.pm > 0 ? 2 : 1;
   const long budget = env_long("RI_PPL_W_BYTES", 16L << 30);
@@ -476,23 +447,6 @@ static void launch_contract(int ntw, const double* W, const double* T, long K, l
   }
 }
 
-// Valid (a <= b) and (a < b) virtual pairs inside block pairs [p0, p0 + n).
-static void count_pairs(const Plan& p, long p0, long n, double& le, double& lt) {
-  le = lt = 0;
-  for (long q = p0; q < p0 + n; ++q) {
-    int X, Y;
-    tri_decode(q, X, Y);
-    const double nx = std::min(TB, p.v - X * TB), ny = std::min(TB, p.v - Y * TB);
-    if (X < Y) {
-      le += nx * ny;
-      lt += nx * ny;
-    } else {
-      le += nx * (nx + 1) / 2;
-      lt += nx * (nx - 1) / 2;
-    }
-  }
-}
-
 static int run_f64(const Plan& p, const double* B_vv, long qs, long rs, const double* tau, double* R,
                    void* ws, hipStream_t s) {
   Carve cv(ws, p.bytes);
@@ -524,7 +478,7 @@ static int run_f64(const Plan& p, const double* B_vv, long qs, long rs, const do
     const long npairs = (p.nbp - slab0) < p.slab_bp ? (p.nbp - slab0) : p.slab_bp;
     const long M = npairs * 256;
     double le, lt;
-    count_pairs(p, slab0, npairs, le, lt);
+    count_pairs(p.v, slab0, npairs, le, lt);
     {
       // per valid (a <= b): the v x v matrix (ac|bd) over all c, d, naux products each
       ProfScope ps(s, "build_w_f64", 2.0 * p.naux * vv * le);
@@ -543,7 +497,7 @@ static int run_f64(const Plan& p, const double* B_vv, long qs, long rs, const do
     }
     {
       ProfScope ps(s, "unpack_f64", 0.0, 16.0 * oo * (le + lt));
-      unpack_f64<<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R);
+      unpack_kernel<double><<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R);
       RI_TRY(check_launch("unpack_f64"));
     }
   }
@@ -559,6 +513,7 @@ int ppl_strided(const double* B, long qs, long rs, const double* tau, int o, int
     set_error("ladder: invalid sizes o=%d v=%d naux=%d", o, v, naux);
     return RI_E_ARG;
   }
+  if (precision == RI_PREC_BF16X3) return ppl::bf16x3_run(B, qs, rs, tau, o, v, naux, R, nullptr, 0, s);
   if (precision != RI_PREC_FP64) {
     set_error("ladder: precision %d not available in this build", precision);
     return RI_E_UNSUPPORTED;
@@ -578,6 +533,7 @@ extern "C" {
 
 size_t ri_ppl_workspace_bytes(int o, int v, int naux, int precision) {
   ppl::Plan p;
+  if (precision == RI_PREC_BF16X3) return ppl::bf16x3_workspace_bytes(o, v, naux);
   if (precision != RI_PREC_FP64) return 0;
   if (!ppl::make_plan(o, v, naux, p)) return 0;
   return p.bytes;
@@ -606,7 +562,7 @@ int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, dou
     set_error("ri_ppl: invalid sizes o=%d v=%d naux=%d", o, v, naux);
     return RI_E_ARG;
   }
-  if (precision != RI_PREC_FP64) {
+  if (precision == RI_PREC_FP32) {
     set_error("ri_ppl: precision %d not available in this build", precision);
     return RI_E_UNSUPPORTED;
   }
@@ -622,6 +578,12 @@ int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, dou
     return RI_E_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ws && (reinterpret_cast<uintptr_t>(ws) & 255)) {
+    set_error("ri_ppl: workspace must be 256-byte aligned");
+    return RI_E_ARG;
+  }
+  if (precision == RI_PREC_BF16X3)
+    return ppl::bf16x3_run(B_vv, static_cast<long>(v) * v, v, tau, o, v, naux, R, ws, ws_bytes, s);
   void* buf = ws;
   bool own = false;
   if (ws) {

@@ -1,0 +1,538 @@
+// Particle-particle ladder, mixed precision: split-bf16 with three products and FP32
+// accumulation on bf16 MFMA (gfx950).
+//
+// Every FP64 operand x is split as x = hi + lo with hi = bf16(x) and lo = bf16(x - hi)
+// (round to nearest even), and each product is formed as hi*hi + hi*lo + lo*hi
+// (the lo*lo term, ~2^-16 relative, is dropped) with FP32 accumulation.  The
+// algorithm is the one of the FP64 path (Sec. II.C, eq. pp-Ladder-0 with Scuseria's
+// split): build W+- = (ac|bd) +- (ad|bc) tile by tile over the RI index, contract
+// with packed tau+-, unpack the mirrored entries into the FP64 R.
+//
+// Layouts (bf16 stored as 16-bit words):
+//   Bh/Bl [c][a][Q]        factors, Q contiguous (padded to 32): one 16-byte run holds
+//                          the 8 consecutive Q a lane feeds to one MFMA
+//   Th/Tl [ij][slot]       packed tau+- (or tau-), slots contiguous
+//   Wh/Wl [ab slot][slot]  build output, already split, slots contiguous
+// Within a cd block pair the 256 slots are ordered so that the 8 (c, d) pairs one
+// wave of the build owns are consecutive: slot = quarter*64 + wave*8 + i*4 + j with
+// c = 8*(quarter>>1) + 2*(wave>>1) + i, d = 8*(quarter&1) + 4*(wave&1) + j.  A lane
+// then stores its 8 results for one (a, b) as one 16-byte run per array.
+//
+// MFMA v_mfma_f32_16x16x32_bf16 lane layout (measured): A[m][k] at lane m + 16*(k/8),
+// element k%8; B[k][n] at lane n + 16*(k/8), element k%8; D[m][n] at lane
+// n + 16*(m/4), element m%4.
+#include <cstdint>
+
+#include "ppl_shared.h"
+
+namespace ri {
+namespace ppl {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));  // one 16-byte run
+
+constexpr int QC = 32;  // RI functions per build step (= MFMA K)
+constexpr int KB = 32;  // cd slots per contraction step (= MFMA K)
+constexpr int CBM = 128;  // contraction tile rows
+
+__host__ __device__ inline uint16_t bf16_bits(float f) {
+  // round to nearest even (inputs are finite)
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__host__ __device__ inline float bf16_val(uint16_t h) {
+  return __builtin_bit_cast(float, static_cast<uint32_t>(h) << 16);
+}
+__device__ inline void split_f64(double x, uint16_t& hi, uint16_t& lo) {
+  hi = bf16_bits(static_cast<float>(x));
+  lo = bf16_bits(static_cast<float>(x - static_cast<double>(bf16_val(hi))));
+}
+__device__ inline void split_f32(float x, uint16_t& hi, uint16_t& lo) {
+  hi = bf16_bits(x);
+  lo = bf16_bits(x - bf16_val(hi));
+}
+
+__device__ inline f32x4_t mfma_bf16(bf16x8_t a, bf16x8_t b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// c += a*b with both split: hi*lo + lo*hi first, then hi*hi
+__device__ inline f32x4_t mfma3(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t bl, f32x4_t c) {
+  c = mfma_bf16(ah, bl, c);
+  c = mfma_bf16(al, bh, c);
+  return mfma_bf16(ah, bh, c);
+}
+// The same with the two cross terms in the mirrored order.  Used for (ad|bc) so that
+// at a == b it accumulates exactly the products of (ac|bd) in the same order: the
+// difference V- = (ac|bd) - (ad|bc) is then exactly zero there, as in exact arithmetic.
+__device__ inline f32x4_t mfma3_mirror(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t bl, f32x4_t c) {
+  c = mfma_bf16(al, bh, c);
+  c = mfma_bf16(ah, bl, c);
+  return mfma_bf16(ah, bh, c);
+}
+
+// slot (0..255) of a cd block pair -> (c_in, d_in)
+__host__ __device__ inline void slot_cd(int slot, int& c_in, int& d_in) {
+  const int q = slot >> 6, w = (slot >> 3) & 7, i = (slot >> 2) & 1, j = slot & 3;
+  c_in = 8 * (q >> 1) + 2 * (w >> 1) + i;
+  d_in = 8 * (q & 1) + 4 * (w & 1) + j;
+}
+
+// ---------------------------------------------------------------- split relayout
+// Bh/Bl[c][a][Q] from B[q][a][c] at B + q*qs + a*rs + c (zero padded).
+// grid (Qp/32, vp/32, vp), block 256: one a, a 32 (Q) x 32 (c) tile
+__global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__ B, long qs, long rs, int v,
+                                                      int naux, int vp, int Qp, uint16_t* __restrict__ Bh,
+                                                      uint16_t* __restrict__ Bl) {
+  __shared__ double tile[32][33];
+  const int q0 = blockIdx.x * 32, c0 = blockIdx.y * 32, a = blockIdx.z;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // ty 0..7
+  for (int r = 0; r < 4; ++r) {
+    const int q = q0 + ty + 8 * r, c = c0 + tx;
+    tile[ty + 8 * r][tx] = (q < naux && c < v && a < v) ? B[q * qs + a * rs + c] : 0.0;
+  }
+  __syncthreads();
+  for (int r = 0; r < 4; ++r) {
+    const int c = c0 + ty + 8 * r, q = q0 + tx;
+    if (c >= vp) continue;  // vp is a multiple of 16, the tile of 32
+    uint16_t hi, lo;
+    split_f64(tile[tx][ty + 8 * r], hi, lo);
+    const size_t idx = (static_cast<size_t>(c) * vp + a) * Qp + q;
+    Bh[idx] = hi;
+    Bl[idx] = lo;
+  }
+}
+
+// ---------------------------------------------------------------- split pack
+// Th/Tl[col][pcd*256 + slot]: sign > 0 tau+ (with the 1/2 on c == d) over i<=j columns,
+// sign < 0 tau- over i<j columns; both from the pair-symmetric part of tau.
+// grid (nbp, ncol), block 256
+__global__ __launch_bounds__(256) void pack_tau_bf16_kernel(const double* __restrict__ tau, int o, int v, long K,
+                                                            int sign, uint16_t* __restrict__ Th,
+                                                            uint16_t* __restrict__ Tl) {
+  int Cb, Db;
+  tri_decode(blockIdx.x, Cb, Db);
+  const int col = blockIdx.y, slot = threadIdx.x;
+  int c_in, d_in;
+  slot_cd(slot, c_in, d_in);
+  const int c = Cb * TB + c_in, d = Db * TB + d_in;
+  const int nreal = sign > 0 ? o * (o + 1) / 2 : o * (o - 1) / 2;
+  double val = 0.0;
+  if (d < v && (Cb < Db || c_in <= d_in) && (sign > 0 || c != d) && col < nreal) {
+    int i, j;
+    tri_decode(col, i, j);
+    if (sign < 0) j += 1;
+    const size_t vv = static_cast<size_t>(v) * v;
+    const double* tij = tau + (static_cast<size_t>(i) * o + j) * vv;
+    const double* tji = tau + (static_cast<size_t>(j) * o + i) * vv;
+    const size_t cd = static_cast<size_t>(c) * v + d, dc = static_cast<size_t>(d) * v + c;
+    const double x1 = tij[cd], x2 = tij[dc], x3 = tji[cd], x4 = tji[dc];
+    if (sign > 0) {
+      val = 0.25 * ((x1 + x4) + (x2 + x3));
+      if (c == d) val *= 0.5;
+    } else {
+      val = 0.25 * ((x1 + x4) - (x2 + x3));
+    }
+  }
+  uint16_t hi, lo;
+  split_f64(val, hi, lo);
+  const size_t idx = static_cast<size_t>(col) * K + static_cast<size_t>(blockIdx.x) * 256 + slot;
+  Th[idx] = hi;
+  Tl[idx] = lo;
+}
+
+// ---------------------------------------------------------------- build
+// Same decomposition as the FP64 build: one workgroup = ab block pair x one quarter
+// (8 c by 8 d) of a cd block pair; wave w owns c in {2(w>>1), +1}, d in {4(w&1)..+3}.
+// LDS per buffer: 16-byte runs [x 16][hl 2][e 32][run 4], run index XOR-swizzled with
+// (e>>2)&3 so the 16 lanes reading one run column hit distinct banks.
+// grid (nbp*4, slab_pairs), block 512
+__global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
+                                                      int Qp, int vp, long slab0, long K, int want_minus,
+                                                      uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
+                                                      uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
+  constexpr int RUNS = 16 * 2 * 32 * 4;  // 4096 runs = 64 KB per buffer
+  __shared__ u32x4_t lds[2 * RUNS];
+  const int quarter = blockIdx.x & 3;
+  const long pcd = blockIdx.x >> 2;
+  const long pab_loc = blockIdx.y;
+  int Cb, Db, Ab, Bb;
+  tri_decode(pcd, Cb, Db);
+  tri_decode(slab0 + pab_loc, Ab, Bb);
+  const int c_base = Cb * TB + (quarter >> 1) * 8;
+  const int d_base = Db * TB + (quarter & 1) * 8;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+
+  // staging: 8 runs per thread per step; every run of a thread comes from the same array
+  const int hl_t = (t >> 7) & 1;
+  const uint16_t* src = hl_t ? Bl : Bh;
+  size_t goff[8];
+  int loff[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int id = t + 512 * r;
+    const int x = id >> 8, e = (id >> 2) & 31, run = id & 3;
+    const int cg = x < 8 ? c_base + x : d_base + (x - 8);
+    const int ag = e < 16 ? Ab * TB + e : Bb * TB + (e - 16);
+    goff[r] = (static_cast<size_t>(cg) * vp + ag) * Qp + run * 8;
+    loff[r] = ((x * 2 + hl_t) * 32 + e) * 4 + (run ^ ((e >> 2) & 3));
+  }
+  // fragment addresses (run indices) for this lane
+  const int fe = lane & 15, frun = lane >> 4;
+  const int fsw = frun ^ ((fe >> 2) & 3);  // same swizzle for e and e + 16
+  const int xc0 = (w >> 1) * 2, xd0 = 8 + (w & 1) * 4;
+
+  f32x4_t o1[2][4], o2[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      o1[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      o2[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    }
+
+  const int nsteps = Qp / QC;
+  u32x4_t stage[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const u32x4_t*>(src + goff[r]);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) lds[loff[r]] = stage[r];
+  __syncthreads();
+  for (int st = 0; st < nsteps; ++st) {
+    const int base = (st & 1) * RUNS;
+    const bool more = st + 1 < nsteps;
+    if (more) {
+      const size_t qo = static_cast<size_t>(st + 1) * QC;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const u32x4_t*>(src + goff[r] + qo);
+    }
+    auto frag = [&](int x, int hl, int e_off) -> bf16x8_t {
+      const u32x4_t v = lds[base + ((x * 2 + hl) * 32 + e_off + fe) * 4 + fsw];
+      return __builtin_bit_cast(bf16x8_t, v);
+    };
+    bf16x8_t ac[2][2], bc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int hl = 0; hl < 2; ++hl) {
+        ac[i][hl] = frag(xc0 + i, hl, 0);
+        bc[i][hl] = frag(xc0 + i, hl, 16);
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf16x8_t adh = frag(xd0 + j, 0, 0), adl = frag(xd0 + j, 1, 0);
+      const bf16x8_t bdh = frag(xd0 + j, 0, 16), bdl = frag(xd0 + j, 1, 16);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        o1[i][j] = mfma3(ac[i][0], ac[i][1], bdh, bdl, o1[i][j]);  // (ac|bd)
+        o2[i][j] = mfma3_mirror(adh, adl, bc[i][0], bc[i][1], o2[i][j]);  // (ad|bc)
+      }
+    }
+    if (more) {
+      const int nb = ((st + 1) & 1) * RUNS;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[nb + loff[r]] = stage[r];
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane holds (a_in = 4*(lane>>4) + r, b_in = lane&15) for the wave's 8 slots
+  const size_t slot0 = static_cast<size_t>(pcd) * 256 + quarter * 64 + w * 8;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a_in = 4 * (lane >> 4) + r, b_in = lane & 15;
+    const size_t row = static_cast<size_t>(pab_loc) * 256 + a_in * 16 + b_in;
+    uint16_t ph[8], pl[8], mh[8], ml[8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float v1 = o1[i][j][r], v2 = o2[i][j][r];
+        split_f32(v1 + v2, ph[i * 4 + j], pl[i * 4 + j]);
+        split_f32(v1 - v2, mh[i * 4 + j], ml[i * 4 + j]);
+      }
+    u32x4_t h, l;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      h[k] = static_cast<uint32_t>(ph[2 * k]) | (static_cast<uint32_t>(ph[2 * k + 1]) << 16);
+      l[k] = static_cast<uint32_t>(pl[2 * k]) | (static_cast<uint32_t>(pl[2 * k + 1]) << 16);
+    }
+    *reinterpret_cast<u32x4_t*>(Wph + row * K + slot0) = h;
+    *reinterpret_cast<u32x4_t*>(Wpl + row * K + slot0) = l;
+    if (want_minus) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        h[k] = static_cast<uint32_t>(mh[2 * k]) | (static_cast<uint32_t>(mh[2 * k + 1]) << 16);
+        l[k] = static_cast<uint32_t>(ml[2 * k]) | (static_cast<uint32_t>(ml[2 * k + 1]) << 16);
+      }
+      *reinterpret_cast<u32x4_t*>(Wmh + row * K + slot0) = h;
+      *reinterpret_cast<u32x4_t*>(Wml + row * K + slot0) = l;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- contract
+// C[m][n] = sum_k W[m][k] T[n][k] (both split); tile 128 (m) x 16*NTW (n); four waves,
+// wave w owns rows 32w..32w+31 (two m tiles) and all columns.  LDS holds 16-byte runs
+// [row][hl 2][run 4], run index swizzled with (row>>2)&3.
+// grid (ncol/(16*NTW), rows/128), block 256
+template <int NTW>
+__global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
+                                                       const uint16_t* __restrict__ Th, const uint16_t* __restrict__ Tl,
+                                                       long K, int ncol, float* __restrict__ C) {
+  constexpr int BN = 16 * NTW;
+  constexpr int ARUNS = CBM * 2 * 4, BRUNS = BN * 2 * 4;
+  __shared__ u32x4_t sA[2 * ARUNS];
+  __shared__ u32x4_t sB[2 * BRUNS];
+  const long n0 = static_cast<long>(blockIdx.x) * BN, m0 = static_cast<long>(blockIdx.y) * CBM;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+
+  // staging: A 1024 runs (4 per thread), B 8*BN runs (ceil(BN/32) per thread)
+  constexpr int BPER = (BRUNS + 255) / 256;
+  size_t aoff[4];
+  int alo[4];
+  const uint16_t* asrc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int id = t + 256 * r;
+    const int row = id >> 3, hl = (id >> 2) & 1, run = id & 3;
+    asrc[r] = hl ? Wl : Wh;
+    aoff[r] = static_cast<size_t>(m0 + row) * K + run * 8;
+    alo[r] = (row * 2 + hl) * 4 + (run ^ ((row >> 2) & 3));
+  }
+  size_t boff[BPER];
+  int blo[BPER];
+  const uint16_t* bsrc[BPER];
+#pragma unroll
+  for (int r = 0; r < BPER; ++r) {
+    const int id = t + 256 * r;
+    const int row = (id >> 3) < BN ? (id >> 3) : 0, hl = (id >> 2) & 1, run = id & 3;
+    bsrc[r] = hl ? Tl : Th;
+    boff[r] = static_cast<size_t>(n0 + row) * K + run * 8;
+    blo[r] = id < BRUNS ? (row * 2 + hl) * 4 + (run ^ ((row >> 2) & 3)) : -1;
+  }
+  const int fr = lane & 15, frun = lane >> 4;
+  const int fsw = frun ^ ((fr >> 2) & 3);
+
+  f32x4_t acc[2][NTW];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) acc[i][u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  const long nsteps = K / KB;
+  u32x4_t ra[4], rb[BPER];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) ra[r] = *reinterpret_cast<const u32x4_t*>(asrc[r] + aoff[r]);
+#pragma unroll
+  for (int r = 0; r < BPER; ++r)
+    if (blo[r] >= 0) rb[r] = *reinterpret_cast<const u32x4_t*>(bsrc[r] + boff[r]);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sA[alo[r]] = ra[r];
+#pragma unroll
+  for (int r = 0; r < BPER; ++r)
+    if (blo[r] >= 0) sB[blo[r]] = rb[r];
+  __syncthreads();
+  for (long st = 0; st < nsteps; ++st) {
+    const int ab = (st & 1) * ARUNS, bb = (st & 1) * BRUNS;
+    const bool more = st + 1 < nsteps;
+    if (more) {
+      const size_t ko = static_cast<size_t>(st + 1) * KB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ra[r] = *reinterpret_cast<const u32x4_t*>(asrc[r] + aoff[r] + ko);
+#pragma unroll
+      for (int r = 0; r < BPER; ++r)
+        if (blo[r] >= 0) rb[r] = *reinterpret_cast<const u32x4_t*>(bsrc[r] + boff[r] + ko);
+    }
+    bf16x8_t a[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int hl = 0; hl < 2; ++hl)
+        a[i][hl] = __builtin_bit_cast(bf16x8_t, sA[ab + ((w * 32 + i * 16 + fr) * 2 + hl) * 4 + fsw]);
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) {
+      const bf16x8_t bh = __builtin_bit_cast(bf16x8_t, sB[bb + ((u * 16 + fr) * 2 + 0) * 4 + fsw]);
+      const bf16x8_t bl = __builtin_bit_cast(bf16x8_t, sB[bb + ((u * 16 + fr) * 2 + 1) * 4 + fsw]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[i][u] = mfma3(a[i][0], a[i][1], bh, bl, acc[i][u]);
+    }
+    if (more) {
+      const int na = ((st + 1) & 1) * ARUNS, nbb = ((st + 1) & 1) * BRUNS;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sA[na + alo[r]] = ra[r];
+#pragma unroll
+      for (int r = 0; r < BPER; ++r)
+        if (blo[r] >= 0) sB[nbb + blo[r]] = rb[r];
+    }
+    __syncthreads();
+  }
+  // D[m][n]: lane n + 16*(m/4), element m%4
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long row = m0 + w * 32 + i * 16 + 4 * (lane >> 4) + r;
+        C[row * ncol + n0 + u * 16 + (lane & 15)] = acc[i][u][r];
+      }
+}
+
+// ---------------------------------------------------------------- host
+struct MPlan {
+  int o, v, naux, nb, vp, Qp;
+  long nbp, K;
+  int po, pm, NP, NM, ntw_p, ntw_m;
+  long slab_bp, slab_M;
+  size_t n_B, n_Tp, n_Tm, n_W, n_S, n_A;  // element counts
+  size_t bytes;
+};
+
+static bool make_mplan(int o, int v, int naux, MPlan& p) {
+  if (o <= 0 || v <= 0 || naux <= 0 || o > 4096 || v > 65536 || naux > (1 << 24)) return false;
+  p.o = o;
+  p.v = v;
+  p.naux = naux;
+  p.nb = (v + TB - 1) / TB;
+  p.vp = p.nb * TB;
+  p.Qp = static_cast<int>(round_up(naux, QC));
+  p.nbp = static_cast<long>(p.nb) * (p.nb + 1) / 2;
+  p.K = p.nbp * 256;
+  p.po = o * (o + 1) / 2;
+  p.pm = o * (o - 1) / 2;
+  pick_ntw(p.po, 9, p.ntw_p, p.NP);
+  pick_ntw(p.pm, 9, p.ntw_m, p.NM);
+  if (p.pm == 0) p.NM = 0;
+  const int nw = p.pm > 0 ? 2 : 1;
+  const long budget = env_long("RI_PPL_W_BYTES", 16L << 30);
+  long bp = budget / (static_cast<long>(nw) * p.K * 256 * 4);
+  bp = std::max(1L, std::min(bp, std::min(p.nbp, 65535L)));
+  const long cap = env_long("RI_PPL_SLAB_PAIRS", bp);
+  p.slab_bp = std::min(cap, bp);
+  p.slab_M = p.slab_bp * 256;
+  p.n_B = static_cast<size_t>(p.vp) * p.vp * p.Qp;
+  p.n_Tp = static_cast<size_t>(p.NP) * p.K;
+  p.n_Tm = static_cast<size_t>(p.NM) * p.K;
+  p.n_W = static_cast<size_t>(p.slab_M) * p.K;
+  p.n_S = static_cast<size_t>(p.slab_M) * p.NP;
+  p.n_A = static_cast<size_t>(p.slab_M) * p.NM;
+  size_t b = 0;
+  // 16-bit: Bh, Bl, Tph, Tpl, Tmh, Tml, Wph, Wpl, Wmh, Wml; 32-bit: S, A
+  for (size_t n : {p.n_B, p.n_B, p.n_Tp, p.n_Tp, p.n_Tm, p.n_Tm, p.n_W, p.n_W, p.pm > 0 ? p.n_W : 0,
+                   p.pm > 0 ? p.n_W : 0})
+    b = round_up(b, 256) + n * 2;
+  for (size_t n : {p.n_S, p.n_A}) b = round_up(b, 256) + n * 4;
+  p.bytes = round_up(b, 256);
+  return true;
+}
+
+template <int NTW>
+static void launch_c(const uint16_t* Wh, const uint16_t* Wl, const uint16_t* Th, const uint16_t* Tl, long K,
+                     long rows, int ncol, float* C, hipStream_t s) {
+  contract_bf16x3<NTW><<<dim3(ncol / (16 * NTW), rows / CBM), 256, 0, s>>>(Wh, Wl, Th, Tl, K, ncol, C);
+}
+
+static void launch_contract(int ntw, const uint16_t* Wh, const uint16_t* Wl, const uint16_t* Th, const uint16_t* Tl,
+                            long K, long rows, int ncol, float* C, hipStream_t s) {
+  switch (ntw) {
+    case 1: launch_c<1>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+    case 2: launch_c<2>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+    case 3: launch_c<3>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+    case 4: launch_c<4>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+    case 5: launch_c<5>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+    case 6: launch_c<6>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+    case 7: launch_c<7>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+    case 8: launch_c<8>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+    default: launch_c<9>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+  }
+}
+
+size_t bf16x3_workspace_bytes(int o, int v, int naux) {
+  MPlan p;
+  return make_mplan(o, v, naux, p) ? p.bytes : 0;
+}
+
+int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R, void* ws,
+               size_t ws_bytes, hipStream_t s) {
+  MPlan p;
+  if (!make_mplan(o, v, naux, p)) {
+    set_error("ladder: invalid sizes o=%d v=%d naux=%d", o, v, naux);
+    return RI_E_ARG;
+  }
+  void* buf = ws;
+  bool own = false;
+  if (!buf) {
+    RI_TRY(dev_alloc(&buf, p.bytes, s));
+    own = true;
+  } else if (ws_bytes < p.bytes) {
+    set_error("ladder: workspace of %zu bytes is smaller than the %zu required", ws_bytes, p.bytes);
+    return RI_E_NOMEM;
+  }
+  Carve cv(buf, p.bytes);
+  uint16_t* Bh = cv.take<uint16_t>(p.n_B);
+  uint16_t* Bl = cv.take<uint16_t>(p.n_B);
+  uint16_t* Tph = cv.take<uint16_t>(p.n_Tp);
+  uint16_t* Tpl = cv.take<uint16_t>(p.n_Tp);
+  uint16_t* Tmh = cv.take<uint16_t>(p.n_Tm);
+  uint16_t* Tml = cv.take<uint16_t>(p.n_Tm);
+  uint16_t* Wph = cv.take<uint16_t>(p.n_W);
+  uint16_t* Wpl = cv.take<uint16_t>(p.n_W);
+  uint16_t* Wmh = cv.take<uint16_t>(p.pm > 0 ? p.n_W : 0);
+  uint16_t* Wml = cv.take<uint16_t>(p.pm > 0 ? p.n_W : 0);
+  float* S = cv.take<float>(p.n_S);
+  float* A = cv.take<float>(p.n_A);
+
+  int rc = RI_OK;
+  const double vv = static_cast<double>(v) * v, oo = static_cast<double>(o) * o;
+  const double pv = v * (v + 1.0) / 2, pvm = v * (v - 1.0) / 2;
+  do {
+    {
+      ProfScope ps(s, "split_b_bf16", 0.0, 8.0 * vv * naux + 4.0 * vv * naux);
+      split_b_kernel<<<dim3(p.Qp / 32, p.vp / 32 + (p.vp % 32 ? 1 : 0), p.vp), 256, 0, s>>>(B, qs, rs, v, naux, p.vp,
+                                                                                           p.Qp, Bh, Bl);
+      if ((rc = check_launch("split_b_kernel"))) break;
+    }
+    {
+      ProfScope ps(s, "pack_tau_bf16", 0.0, 8.0 * oo * vv + 4.0 * (pv * p.po + pvm * p.pm));
+      pack_tau_bf16_kernel<<<dim3(p.nbp, p.NP), 256, 0, s>>>(tau, o, v, p.K, +1, Tph, Tpl);
+      if ((rc = check_launch("pack_tau_bf16(+)"))) break;
+      if (p.pm > 0) {
+        pack_tau_bf16_kernel<<<dim3(p.nbp, p.NM), 256, 0, s>>>(tau, o, v, p.K, -1, Tmh, Tml);
+        if ((rc = check_launch("pack_tau_bf16(-)"))) break;
+      }
+    }
+    for (long slab0 = 0; slab0 < p.nbp && rc == RI_OK; slab0 += p.slab_bp) {
+      const long npairs = std::min(p.slab_bp, p.nbp - slab0);
+      const long M = npairs * 256;
+      double le, lt;
+      count_pairs(v, slab0, npairs, le, lt);
+      {
+        ProfScope ps(s, "build_w_bf16x3", 2.0 * naux * vv * le);
+        build_w_bf16x3<<<dim3(p.nbp * 4, npairs), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K, p.pm > 0 ? 1 : 0,
+                                                              Wph, Wpl, Wmh, Wml);
+        if ((rc = check_launch("build_w_bf16x3"))) break;
+      }
+      {
+        ProfScope ps(s, "contract_bf16x3", 2.0 * (le * pv * p.po + lt * pvm * p.pm));
+        launch_contract(p.ntw_p, Wph, Wpl, Tph, Tpl, p.K, M, p.NP, S, s);
+        if ((rc = check_launch("contract_bf16x3(+)"))) break;
+        if (p.pm > 0) {
+          launch_contract(p.ntw_m, Wmh, Wml, Tmh, Tml, p.K, M, p.NM, A, s);
+          if ((rc = check_launch("contract_bf16x3(-)"))) break;
+        }
+      }
+      {
+        ProfScope ps(s, "unpack_f32", 0.0, 16.0 * oo * (le + lt));
+        launch_unpack_f32(S, A, p.NP, p.NM, o, v, slab0, npairs, R, s);
+        if ((rc = check_launch("unpack_f32"))) break;
+      }
+    }
+  } while (false);
+  if (own) dev_free(buf, s);
+  return rc;
+}
+
+}  // namespace ppl
+}  // namespace ri

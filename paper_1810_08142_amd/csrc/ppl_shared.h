@@ -1,0 +1,76 @@
+// Helpers shared by the ladder paths (internal).
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+#include "ri_common.h"
+
+namespace ri {
+namespace ppl {
+
+constexpr int TB = 16;  // virtual block size: a block pair (X <= Y) has 256 slots
+constexpr int NG = 16;  // column granule of the packed amplitudes
+
+__host__ __device__ inline void tri_decode(long p, int& x, int& y) {
+  // p = y(y+1)/2 + x with 0 <= x <= y
+  long yy = static_cast<long>((sqrt(8.0 * static_cast<double>(p) + 1.0) - 1.0) * 0.5);
+  while ((yy + 1) * (yy + 2) / 2 <= p) ++yy;
+  while (yy * (yy + 1) / 2 > p) --yy;
+  y = static_cast<int>(yy);
+  x = static_cast<int>(p - yy * (yy + 1) / 2);
+}
+
+// Contraction column tiling: ntw 16-wide column tiles per workgroup tile (1..maxw),
+// chosen to minimise the padded column count (ties: wider tiles).
+inline void pick_ntw(int ncols, int maxw, int& ntw, int& padded) {
+  const int n16 = std::max(1, (ncols + NG - 1) / NG);
+  ntw = 1;
+  int best = 1 << 30;
+  for (int c = 1; c <= maxw; ++c) {
+    const int p = (n16 + c - 1) / c * c;
+    if (p < best || (p == best && c > ntw)) {
+      best = p;
+      ntw = c;
+    }
+  }
+  padded = best * NG;
+}
+
+inline long env_long(const char* name, long dflt) {
+  const char* s = getenv(name);
+  if (!s || !*s) return dflt;
+  char* end = nullptr;
+  long x = strtol(s, &end, 10);
+  return (end && *end == 0 && x > 0) ? x : dflt;
+}
+
+// Valid (a <= b) and (a < b) virtual pairs inside block pairs [p0, p0 + n).
+inline void count_pairs(int v, long p0, long n, double& le, double& lt) {
+  le = lt = 0;
+  for (long q = p0; q < p0 + n; ++q) {
+    int X, Y;
+    tri_decode(q, X, Y);
+    const double nx = std::min(TB, v - X * TB), ny = std::min(TB, v - Y * TB);
+    if (X < Y) {
+      le += nx * ny;
+      lt += nx * ny;
+    } else {
+      le += nx * (nx + 1) / 2;
+      lt += nx * (nx - 1) / 2;
+    }
+  }
+}
+
+// R += mirrored S +- A from FP32 slab results (shared unpack kernel).
+void launch_unpack_f32(const float* S, const float* A, int NP, int NM, int o, int v, long slab0, long npairs,
+                       double* R, hipStream_t s);
+
+// Mixed-precision ladder (split-bf16, three products, FP32 accumulation).
+size_t bf16x3_workspace_bytes(int o, int v, int naux);
+int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
+               void* ws, size_t ws_bytes, hipStream_t s);
+
+}  // namespace ppl
+}  // namespace ri

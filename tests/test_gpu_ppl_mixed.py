@@ -1,0 +1,104 @@
+"""Mixed-precision ladder (split-bf16, three products, FP32 accumulation) on the GPU.
+
+Error model: a split operand x = hi + lo is exact to 2^-18 |x|, and dropping lo*lo
+adds another 2^-18 |a||b|, so one split product is within 3 * 2^-18 |a||b|.  The
+build and the contraction each split once and accumulate in FP32, hence, element
+by element,
+
+    |R_mixed - R_fp64| <= eps * sum_cd sum_Q |B_ac| |B_bd| |tau^{cd}_{ij}|  = eps * L(|B|, |tau|)
+
+with eps = 2e-4 (two split stages, FP32 accumulation over up to ~1e4 terms).  The
+right-hand side is the oracle's ladder of the element-wise absolute values."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import dev, host
+from oracle import ccsd as oc
+from oracle import native
+from paper_1810_08142_amd.synthetic import CONFIGS, draw_matrix, draw_pair_symmetric, draw_system
+
+pytestmark = pytest.mark.gpu
+EPS = 2e-4
+
+
+def _ladder(B_vv, tau, precision="bf16x3"):
+    import torch
+    from paper_1810_08142_amd import ppl
+    o, v = tau.shape[0], tau.shape[2]
+    R = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    ppl.ppl(dev(B_vv), dev(tau), R, precision=precision)
+    return host(R)
+
+
+@pytest.mark.parametrize("o,v,naux", [(1, 3, 2), (2, 17, 7), (3, 33, 20), (4, 24, 96), (5, 40, 37), (2, 50, 130)])
+def test_mixed_within_split_error_bound(o, v, naux):
+    print(f"bf16x3 o={o} v={v} naux={naux}", flush=True)
+    s = draw_system(o, v, naux, seed=900 + v)
+    tau = draw_pair_symmetric(o, v, 901 + v)
+    got = _ladder(s.B_vv, tau)
+    ref = native.ppl(s.B_vv, tau)
+    bound = EPS * native.ppl(np.abs(s.B_vv), np.abs(tau))
+    err = np.abs(got - ref)
+    print("max rel err", float(err.max() / np.abs(ref).max()), "max err/bound", float((err / bound).max()))
+    assert bool(np.all(err <= bound))
+    # and it is not accidentally the FP64 result: the split error is visible
+    assert float(err.max()) > 0.0
+
+
+def test_mixed_nonsymmetric_factors_and_symmetry():
+    o, v, naux = 3, 29, 17
+    s = draw_system(o, v, naux, seed=911, scale=0.2)
+    t1 = draw_matrix((o, v), 912, 0.1)
+    Bd = np.ascontiguousarray(oc.dress(s.B, t1)[:, o:, o:])
+    tau = draw_pair_symmetric(o, v, 913)
+    got = _ladder(Bd, tau)
+    ref = native.ppl(Bd, tau)
+    assert bool(np.all(np.abs(got - ref) <= EPS * native.ppl(np.abs(Bd), np.abs(tau))))
+    # exact pair symmetry needs (ac|bd) - (ad|bc) to vanish exactly at a == b
+    assert np.array_equal(got, got.transpose(1, 0, 3, 2))
+    assert np.array_equal(got, _ladder(Bd, tau))
+
+
+def test_mixed_slabs_do_not_change_result():
+    o, v, naux = 3, 70, 18
+    s = draw_system(o, v, naux, seed=921)
+    tau = draw_pair_symmetric(o, v, 922)
+    R1 = _ladder(s.B_vv, tau)
+    os.environ["RI_PPL_SLAB_PAIRS"] = "3"
+    try:
+        R2 = _ladder(s.B_vv, tau)
+    finally:
+        del os.environ["RI_PPL_SLAB_PAIRS"]
+    assert np.array_equal(R1, R2)
+
+
+def test_mixed_c2_full_size_sampled():
+    c = CONFIGS["c2"]
+    o, v, naux = c["o"], c["v"], c["naux"]
+    s = draw_system(o, v, naux, seed=c["seed"])
+    _, t2, _ = oc.mp2(s.B, s.eps, o)
+    tau = oc.make_tau(s.t1, t2)
+    R = _ladder(s.B_vv, tau)
+    rng = np.random.default_rng(8)
+    pairs = [(int(a), int(b)) for a, b in rng.integers(0, v, size=(24, 2))] + [(0, 0), (v - 1, 0)]
+    ref = native.ppl_pairs(s.B_vv, tau, pairs)
+    bound = EPS * native.ppl_pairs(np.abs(s.B_vv), np.abs(tau), pairs)
+    got = np.stack([R[:, :, a, b] for a, b in pairs])
+    print("c2 bf16x3 max rel err", float(np.abs(got - ref).max() / np.abs(ref).max()), flush=True)
+    assert bool(np.all(np.abs(got - ref) <= bound))
+    assert np.array_equal(R, R.transpose(1, 0, 3, 2))
+
+
+def test_ccsd_with_mixed_ladder_energy_within_microhartree():
+    from paper_1810_08142_amd import ccsd
+    c = CONFIGS["c1"]
+    o, v, naux = c["o"], c["v"], c["naux"]
+    s = draw_system(o, v, naux, seed=c["seed"])
+    B, eps = dev(s.B), dev(s.eps)
+    _, _, r64 = ccsd.solve(B, eps, o)
+    _, _, rmx = ccsd.solve(B, eps, o, ppl_precision="bf16x3", tol=1e-8, tol_energy=1e-9)
+    print("E fp64", r64.e_corr, "E bf16x3", rmx.e_corr, "diff", rmx.e_corr - r64.e_corr, flush=True)
+    assert r64.converged and rmx.converged
+    assert abs(rmx.e_corr - r64.e_corr) <= 1e-6
