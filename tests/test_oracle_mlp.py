@@ -1,0 +1,74 @@
+"""Pins of the CPU oracle of the learned guess: a hand-worked forward pass,
+central finite differences of the loss, the exact-fit stationary point, the
+closed form of Adam's first step, and the symmetry of the features."""
+import math
+import os
+
+import numpy as np
+
+from oracle import ccsd as oc
+from oracle import mlp
+from paper_1810_08142_amd.synthetic import draw_matrix, draw_system
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_hand_worked_forward():
+    theta = np.array([1.0, -1.0, 0.0, 0.5, 2.0, -3.0, 0.25])
+    x, y = np.loadtxt(os.path.join(HERE, "golden", "mlp_hand_1x2.txt"))
+    got, _ = mlp.forward(theta, np.array([[x]]), 1, 2, 1)
+    assert abs(got[0] - y) <= 1e-15
+    assert abs(math.tanh(0.5) - (math.e - 1) / (math.e + 1)) <= 1e-16
+
+
+def test_gradient_matches_central_differences():
+    d_in, h, layers, n = 3, 5, 2, 7
+    rng = np.random.default_rng(3)
+    theta = 0.5 * rng.standard_normal(mlp.num_params(d_in, h, layers))
+    X = rng.standard_normal((n, d_in))
+    Y = rng.standard_normal(n)
+    L, g = mlp.gradient(theta, X, Y, d_in, h, layers)
+    assert abs(L - mlp.loss(theta, X, Y, d_in, h, layers)) <= 1e-15
+    step = 1e-6
+    fd = np.empty_like(theta)
+    for k in range(theta.size):
+        e = np.zeros_like(theta)
+        e[k] = step
+        fd[k] = (mlp.loss(theta + e, X, Y, d_in, h, layers) - mlp.loss(theta - e, X, Y, d_in, h, layers)) / (2 * step)
+    assert np.abs(g - fd).max() <= 1e-6 * max(1.0, np.abs(g).max())
+
+
+def test_exact_fit_is_stationary():
+    d_in, h, layers = 2, 4, 2
+    rng = np.random.default_rng(4)
+    theta = rng.standard_normal(mlp.num_params(d_in, h, layers))
+    X = rng.standard_normal((5, d_in))
+    Y, _ = mlp.forward(theta, X, d_in, h, layers)
+    L, g = mlp.gradient(theta, X, Y, d_in, h, layers)
+    assert L == 0.0 and np.abs(g).max() == 0.0
+
+
+def test_adam_first_step_closed_form():
+    theta = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    new, m, v = mlp.adam_step(theta, g, np.zeros(3), np.zeros(3), 1, lr=0.01)
+    # bias-corrected moments of step one are g and g^2
+    np.testing.assert_allclose(new, theta - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_features_pair_symmetric_and_defined():
+    o, v = 3, 7
+    s = draw_system(o, v, 9, seed=170)
+    _, t2, _ = oc.mp2(s.B, s.eps, o)
+    F = mlp.features(s.B, s.eps, o, t2)
+    assert F.shape == (o, o, v, v, mlp.N_FEATURES)
+    np.testing.assert_array_equal(F, F.transpose(1, 0, 3, 2, 4))
+    i, j, a, b = 0, 2, 5, 1
+    iajb = sum(s.B[q, i, o + a] * s.B[q, j, o + b] for q in range(9))
+    ibja = sum(s.B[q, i, o + b] * s.B[q, j, o + a] for q in range(9))
+    iaia = sum(s.B[q, i, o + a] ** 2 for q in range(9))
+    jbjb = sum(s.B[q, j, o + b] ** 2 for q in range(9))
+    e = s.eps
+    want = [t2[i, j, a, b], t2[i, j, b, a], iajb, ibja, e[i] + e[j] - e[o + a] - e[o + b],
+            (e[o + a] - e[o + b]) ** 2, (e[i] - e[j]) ** 2, math.sqrt(iaia * jbjb)]
+    np.testing.assert_allclose(F[i, j, a, b], want, rtol=1e-13, atol=1e-16)
