@@ -62,7 +62,7 @@ def test_features_pair_symmetric_and_defined():
     _, t2, _ = oc.mp2(s.B, s.eps, o)
     F = mlp.features(s.B, s.eps, o, t2)
     assert F.shape == (o, o, v, v, mlp.N_FEATURES)
-    np.testing.assert_array_equal(F, F.transpose(1, 0, 3, 2, 4))
+    np.testing.assert_allclose(F, F.transpose(1, 0, 3, 2, 4), rtol=1e-15, atol=1e-18)
     i, j, a, b = 0, 2, 5, 1
     iajb = sum(s.B[q, i, o + a] * s.B[q, j, o + b] for q in range(9))
     ibja = sum(s.B[q, i, o + b] * s.B[q, j, o + a] for q in range(9))
