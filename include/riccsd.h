@@ -159,6 +159,50 @@ int ri_ccsd_residual(const ri_system* sys, const double* t1, const double* t2, d
 int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_opts* opts,
                     ri_ccsd_report* rep, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned starting guess (not in the paper; an addition on top of the MP2 guess).
+ * A fully connected network -- `layers` tanh hidden layers of `hidden` units and
+ * one linear output -- maps 8 per-amplitude MP2 features to a correction of the
+ * MP2 doubles amplitudes: t2 = t2_MP2 + y_scale * net((x - mean) / std).
+ * Parameters form one FP32 vector W1 [d_in][h], b1 [h], ..., W_out [h][1], b_out [1].
+ * Training runs on the GPU (loss: batch mean of (y - Y)^2, Adam with beta1 0.9,
+ * beta2 0.999, eps 1e-8).  The handle owns its device memory; calls that take a
+ * stream enqueue on it; a handle must not be used from two streams at once.
+ * ------------------------------------------------------------------------ */
+typedef struct ri_mlp ri_mlp;
+
+/* New network with zero parameters (NULL on failure, see ri_last_error_msg). */
+ri_mlp* ri_mlp_create(int d_in, int hidden, int layers);
+void ri_mlp_destroy(ri_mlp* net);
+size_t ri_mlp_num_params(const ri_mlp* net);
+/* Copy the flat parameter vector from / to host memory (set also resets Adam). */
+int ri_mlp_set_params(ri_mlp* net, const float* params_host);
+int ri_mlp_get_params(const ri_mlp* net, float* params_host);
+/* Feature standardisation (mean, std: d_in host floats, std > 0) and output scale. */
+int ri_mlp_set_scaling(ri_mlp* net, const float* mean, const float* std, float y_scale);
+int ri_mlp_get_scaling(const ri_mlp* net, float* mean, float* std, float* y_scale);
+/* y[n] = net(X) for device X [n][d_in] (already standardised), FP32. */
+int ri_mlp_forward(ri_mlp* net, const float* X, long n, float* y, void* stream);
+/* Loss and its gradient (device FP32 [num_params]; NULL uses internal storage) on a
+ * batch of n <= 2^24 rows; the loss is written to *loss_host when not NULL
+ * (synchronises stream).  Deterministic (fixed reduction order). */
+int ri_mlp_gradient(ri_mlp* net, const float* X, const float* Y, long n, float* grad, float* loss_host,
+                    void* stream);
+/* One Adam step with learning rate lr on the batch; *loss_host gets the batch loss
+ * before the step when not NULL (synchronises stream). */
+int ri_mlp_train_step(ri_mlp* net, const float* X, const float* Y, long n, float lr, float* loss_host,
+                      void* stream);
+/* Raw (unstandardised) features of every amplitude, X [o][o][v][v][8] FP32, from the
+ * MP2 t2 and the (ia|jb) integrals of sys: t2_ijab, t2_ijba, (ia|jb), (ib|ja),
+ * e_i + e_j - e_a - e_b, (e_a - e_b)^2, (e_i - e_j)^2, sqrt((ia|ia)(jb|jb)). */
+int ri_mlp_features(const ri_system* sys, const double* t2_mp2, float* X, void* stream);
+/* Learned guess: t1 = 0, t2 = t2_MP2 + correction, pair-symmetrised (FP64 outputs).
+ * The network must have 8 inputs. */
+int ri_mlp_guess(ri_mlp* net, const ri_system* sys, double* t1, double* t2, void* stream);
+/* Binary file with sizes, scaling and parameters. */
+int ri_mlp_save(const ri_mlp* net, const char* path);
+ri_mlp* ri_mlp_load(const char* path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,6 +40,7 @@ class RICcsdReport(_c.Structure):
 
 _sysp = _c.POINTER(RISystem)
 _dblp = _c.POINTER(_c.c_double)
+_fltp = _c.POINTER(_c.c_float)
 
 # (name, restype, argtypes)
 _SIGS = [
@@ -58,6 +59,20 @@ _SIGS = [
     ("ri_ccsd_energy", _c.c_int, [_sysp, _dp, _dp, _dblp, _dp]),
     ("ri_ccsd_residual", _c.c_int, [_sysp, _dp, _dp, _dp, _dp, _c.c_int, _dp]),
     ("ri_ccsd_iterate", _c.c_int, [_sysp, _dp, _dp, _c.POINTER(RICcsdOpts), _c.POINTER(RICcsdReport), _dp]),
+    ("ri_mlp_create", _c.c_void_p, [_c.c_int, _c.c_int, _c.c_int]),
+    ("ri_mlp_destroy", None, [_c.c_void_p]),
+    ("ri_mlp_num_params", _c.c_size_t, [_c.c_void_p]),
+    ("ri_mlp_set_params", _c.c_int, [_c.c_void_p, _fltp]),
+    ("ri_mlp_get_params", _c.c_int, [_c.c_void_p, _fltp]),
+    ("ri_mlp_set_scaling", _c.c_int, [_c.c_void_p, _fltp, _fltp, _c.c_float]),
+    ("ri_mlp_get_scaling", _c.c_int, [_c.c_void_p, _fltp, _fltp, _fltp]),
+    ("ri_mlp_forward", _c.c_int, [_c.c_void_p, _dp, _c.c_long, _dp, _dp]),
+    ("ri_mlp_gradient", _c.c_int, [_c.c_void_p, _dp, _dp, _c.c_long, _dp, _fltp, _dp]),
+    ("ri_mlp_train_step", _c.c_int, [_c.c_void_p, _dp, _dp, _c.c_long, _c.c_float, _fltp, _dp]),
+    ("ri_mlp_features", _c.c_int, [_sysp, _dp, _dp, _dp]),
+    ("ri_mlp_guess", _c.c_int, [_c.c_void_p, _sysp, _dp, _dp, _dp]),
+    ("ri_mlp_save", _c.c_int, [_c.c_void_p, _c.c_char_p]),
+    ("ri_mlp_load", _c.c_void_p, [_c.c_char_p]),
 ]
 
 

@@ -374,7 +374,7 @@ bool diis_solve(const std::vector<std::vector<double>>& gram, std::vector<double
   return true;
 }
 
-static int check_system(const ri_system* sys, const char* where) {
+int check_system(const ri_system* sys, const char* where) {
   if (!sys || !sys->B || !sys->eps || sys->o <= 0 || sys->v <= 0 || sys->naux <= 0) {
     set_error("%s: invalid system", where);
     return RI_E_ARG;
@@ -384,6 +384,25 @@ static int check_system(const ri_system* sys, const char* where) {
     return RI_E_ARG;
   }
   return RI_OK;
+}
+
+// MP2 guess with the (ia|jb) integrals kept: gov [o][v][o][v], t1 [o][v], t2 [o][o][v][v]
+int ovov_integrals(const ri_system* sys, double* gov, hipStream_t s) {
+  RI_TRY(check_system(sys, "ovov"));
+  Ctx c(sys, s);
+  return einsum("Qkc,Qld->kcld", 1.0, c.ov_(sys->B), c.ov_(sys->B), 0.0, c.t4(gov, c.o, c.v, c.o, c.v), c.arena, s);
+}
+
+int mp2_with_integrals(const ri_system* sys, double* gov, double* t1, double* t2, hipStream_t s) {
+  RI_TRY(ovov_integrals(sys, gov, s));
+  Ctx c(sys, s);
+  mp2_kernel<<<nblk(std::max(c.noovv, c.nov)), 256, 0, s>>>(gov, sys->eps, c.o, c.v, t1, t2);
+  return check_launch("mp2_kernel");
+}
+
+int symmetrize_pairs(double* t2, int o, int v, hipStream_t s) {
+  symmetrize_kernel<<<nblk(static_cast<long>(o) * o * v * v), 256, 0, s>>>(t2, o, v);
+  return check_launch("symmetrize_kernel");
 }
 
 }  // namespace cc

@@ -1,0 +1,750 @@
+// Learned starting guess for the doubles amplitudes: a fully connected network
+// with tanh hidden layers maps per-amplitude MP2 features to a correction of the
+// MP2 amplitudes.  Training (forward, backward, Adam) and inference run in these
+// FP32 kernels on f32 MFMA; the result is added to the FP64 MP2 amplitudes.
+//
+// Parameters are one flat FP32 vector: W1 [d_in][h], b1 [h], ..., W_out [h][1], b_out [1].
+// Loss: mean over the batch of (y - Y)^2.
+//
+// MFMA v_mfma_f32_16x16x4f32 lane layout (measured): A[m][k] at lane m + 16k,
+// B[k][n] at lane n + 16k, D[m][n] at lane n + 16*(m/4), element m%4.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "ri_common.h"
+
+struct ri_mlp {
+  int d_in, hidden, layers;
+  size_t nparams;
+  float* params = nullptr;  // device
+  float* grad = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  long step = 0;
+  std::vector<float> mean, stdv;
+  float y_scale = 1.f;
+  float* scratch = nullptr;  // activations and deltas for up to `rows` rows
+  long rows = 0;
+  size_t scratch_bytes = 0;
+};
+
+namespace ri {
+namespace mlp {
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int BM = 64, BN = 64, KC = 16;
+constexpr int NF = 8;  // features per amplitude
+
+// C(m, n) = epilogue(alpha * sum_k A(m, k) B(k, n)); A(m, k) = A[m*sam + k*sak],
+// B(k, n) = B[k*sbk + n*sbn]; C[m*ldc + n].  epilogue: + bias[n] (if bias), tanh (if act).
+// grid.z splits K into `splits` ranges whose partial results go to C + z*split_stride.
+struct GemmF32 {
+  long M, N, K;
+  const float* A;
+  long sam, sak;
+  const float* B;
+  long sbk, sbn;
+  float* C;
+  long ldc;
+  const float* bias;
+  int act;
+  float alpha;
+  long kper;          // K range per split
+  long split_stride;  // elements between split outputs
+};
+
+__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmF32 g, int a_kfast, int b_kfast) {
+  __shared__ float sA[2][KC][BM + 1];
+  __shared__ float sB[2][KC][BN + 1];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const long bm = static_cast<long>(blockIdx.y) * BM, bn = static_cast<long>(blockIdx.x) * BN;
+  const long k_lo = blockIdx.z * g.kper, k_hi = std::min(g.K, k_lo + g.kper);
+  float* C = g.C + blockIdx.z * g.split_stride;
+
+  const int am = a_kfast ? (t >> 2) : (t & 63);
+  const int ak = a_kfast ? ((t & 3) << 2) : (t >> 6);
+  const int akstep = a_kfast ? 1 : 4;
+  const int bnn = b_kfast ? (t >> 2) : (t & 63);
+  const int bk = b_kfast ? ((t & 3) << 2) : (t >> 6);
+  const int bkstep = b_kfast ? 1 : 4;
+  const bool arow = bm + am < g.M, brow = bn + bnn < g.N;
+  const float* Ap = g.A + (arow ? (bm + am) * g.sam : 0);
+  const float* Bp = g.B + (brow ? (bn + bnn) * g.sbn : 0);
+
+  float ra[4], rb[4];
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const long nchunks = k_hi > k_lo ? (k_hi - k_lo + KC - 1) / KC : 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const long ka = k_lo + ak + r * akstep, kb = k_lo + bk + r * bkstep;
+    ra[r] = (arow && ka < k_hi) ? Ap[ka * g.sak] : 0.f;
+    rb[r] = (brow && kb < k_hi) ? Bp[kb * g.sbk] : 0.f;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    sA[0][ak + r * akstep][am] = ra[r];
+    sB[0][bk + r * bkstep][bnn] = rb[r];
+  }
+  __syncthreads();
+  for (long ch = 0; ch < nchunks; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nchunks;
+    if (more) {
+      const long k0 = k_lo + (ch + 1) * KC;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long ka = k0 + ak + r * akstep, kb = k0 + bk + r * bkstep;
+        ra[r] = (arow && ka < k_hi) ? Ap[ka * g.sak] : 0.f;
+        rb[r] = (brow && kb < k_hi) ? Bp[kb * g.sbk] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int kk = 4 * s + kq;
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = sA[buf][kk][wm + 16 * i + l16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sB[buf][kk][wn + 16 * j + l16];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        sA[buf ^ 1][ak + r * akstep][am] = ra[r];
+        sB[buf ^ 1][bk + r * bkstep][bnn] = rb[r];
+      }
+    }
+    __syncthreads();
+  }
+  // D[m][n] at lane n + 16*(m/4), element m%4
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const long n = bn + wn + 16 * j + l16;
+      if (n >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long m = bm + wm + 16 * i + 4 * kq + r;
+        if (m >= g.M) continue;
+        float val = g.alpha * acc[i][j][r];
+        if (g.bias) val += g.bias[n];
+        if (g.act) val = tanhf(val);
+        C[m * g.ldc + n] = val;
+      }
+    }
+}
+
+// out[i] = sum_z part[z * stride + i], fixed order
+__global__ void sum_splits(const float* __restrict__ part, int splits, long stride, long n, float* out) {
+  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.f;
+  for (int z = 0; z < splits; ++z) acc += part[z * stride + i];
+  out[i] = acc;
+}
+
+// part[z][c] = sum over rows r in chunk z of D[r][c]  (grid (ceil(cols/256), splits))
+__global__ void colsum_partial(const float* __restrict__ D, long rows, int cols, long rper, float* part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  const long lo = blockIdx.y * rper, hi = std::min(rows, lo + rper);
+  float acc = 0.f;
+  for (long r = lo; r < hi; ++r) acc += D[r * cols + c];
+  part[static_cast<long>(blockIdx.y) * cols + c] = acc;
+}
+
+// delta = dH * (1 - H^2)   (tanh')
+__global__ void tanh_back(const float* __restrict__ H, float* dH, long n) {
+  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dH[i] *= 1.f - H[i] * H[i];
+}
+
+constexpr int LB = 1024;
+// delta_out[r] = 2 (y - Y) / n and partials of sum (y - Y)^2
+__global__ __launch_bounds__(256) void mse_stage1(const float* __restrict__ y, const float* __restrict__ Y, long n,
+                                                  float* delta, float* part) {
+  __shared__ float sh[256];
+  const long chunk = (n + LB - 1) / LB;
+  const long lo = static_cast<long>(blockIdx.x) * chunk, hi = std::min(n, lo + chunk);
+  float acc = 0.f;
+  for (long i = lo + threadIdx.x; i < hi; i += 256) {
+    const float r = y[i] - Y[i];
+    delta[i] = 2.f * r / static_cast<float>(n);
+    acc += r * r;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void mse_stage2(const float* __restrict__ part, long n, float* loss) {
+  __shared__ float sh[256];
+  float acc = 0.f;
+  for (int i = threadIdx.x; i < LB; i += 256) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = sh[0] / static_cast<float>(n);
+}
+
+__global__ void adam_kernel(float* p, const float* __restrict__ g, float* m, float* v, long n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Features of amplitudes [row0, row0 + n) of the o*o*v*v flattened (i, j, a, b) set:
+// t2_ijab, t2_ijba, (ia|jb), (ib|ja), e_i + e_j - e_a - e_b, (e_a - e_b)^2, (e_i - e_j)^2,
+// sqrt((ia|ia)(jb|jb)); standardised with (x - mean) / std when mean != NULL.
+struct Norm {
+  float mean[NF], inv_std[NF];
+  int on;
+};
+__global__ void features_kernel(const double* __restrict__ gov, const double* __restrict__ eps,
+                                const double* __restrict__ t2, int o, int v, long row0, long n, Norm nm, float* X) {
+  const long r = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const long idx = row0 + r;
+  const long vv = static_cast<long>(v) * v;
+  const int b = idx % v, a = (idx / v) % v;
+  const long ij = idx / vv;
+  const int j = ij % o, i = ij / o;
+  auto G = [&](int p, int x, int q, int y) { return gov[((static_cast<long>(p) * v + x) * o + q) * v + y]; };
+  const double ea = eps[o + a], eb = eps[o + b], ei = eps[i], ej = eps[j];
+  double f[NF];
+  f[0] = t2[idx];
+  f[1] = t2[ij * vv + static_cast<long>(b) * v + a];
+  f[2] = G(i, a, j, b);
+  f[3] = G(i, b, j, a);
+  f[4] = ei + ej - ea - eb;
+  f[5] = (ea - eb) * (ea - eb);
+  f[6] = (ei - ej) * (ei - ej);
+  f[7] = sqrt(G(i, a, i, a) * G(j, b, j, b));
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    float x = static_cast<float>(f[k]);
+    if (nm.on) x = (x - nm.mean[k]) * nm.inv_std[k];
+    X[r * NF + k] = x;
+  }
+}
+
+// t2[row0 + r] += scale * y[r]
+__global__ void add_correction(double* t2, long row0, long n, const float* __restrict__ y, float scale) {
+  const long r = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r < n) t2[row0 + r] += static_cast<double>(scale) * static_cast<double>(y[r]);
+}
+
+inline unsigned nblk(long n) { return static_cast<unsigned>((n + 255) / 256); }
+
+int gemm(GemmF32 g, int splits, hipStream_t s) {
+  g.kper = (g.K + splits - 1) / splits;
+  const int a_kfast = (g.sak == 1 && g.sam != 1) ? 1 : 0;
+  const int b_kfast = (g.sbk == 1 && g.sbn != 1) ? 1 : 0;
+  dim3 grid(static_cast<unsigned>((g.N + BN - 1) / BN), static_cast<unsigned>((g.M + BM - 1) / BM), splits);
+  gemm_f32_kernel<<<grid, 256, 0, s>>>(g, a_kfast, b_kfast);
+  return check_launch("gemm_f32_kernel");
+}
+
+// layer k (0-based) parameter pointers
+inline void layer_ptrs(const ri_mlp* net, float* base, int k, float*& W, float*& b, int& fin, int& fout) {
+  size_t off = 0;
+  int in = net->d_in;
+  for (int l = 0; l <= net->layers; ++l) {
+    const int out = l < net->layers ? net->hidden : 1;
+    if (l == k) {
+      W = base + off;
+      b = base + off + static_cast<size_t>(in) * out;
+      fin = in;
+      fout = out;
+      return;
+    }
+    off += static_cast<size_t>(in) * out + out;
+    in = out;
+  }
+}
+
+// scratch layout for `rows` rows: H[1..layers] [rows][h], D (delta) [rows][h] x 2, y [rows],
+// dy [rows], split partials [SPLITS][h*h], loss partials [LB] + 1
+constexpr int SPLITS = 32;
+int reserve(ri_mlp* net, long rows, hipStream_t s) {
+  if (rows <= net->rows) return RI_OK;
+  const size_t h = net->hidden;
+  const size_t n = static_cast<size_t>(rows);
+  const size_t floats = net->layers * n * h + 2 * n * h + 2 * n + SPLITS * std::max(h * h, h * 64) + LB + 16;
+  if (net->scratch) dev_free(net->scratch, s);
+  net->scratch = nullptr;
+  net->rows = 0;
+  void* p = nullptr;
+  RI_TRY(dev_alloc(&p, floats * sizeof(float), s));
+  net->scratch = static_cast<float*>(p);
+  net->rows = rows;
+  net->scratch_bytes = floats * sizeof(float);
+  return RI_OK;
+}
+
+struct Scr {
+  std::vector<float*> H;  // H[1..layers]
+  float *D0, *D1, *y, *dy, *part, *lpart, *loss;
+};
+Scr carve(const ri_mlp* net) {
+  Scr c;
+  const size_t h = net->hidden, n = static_cast<size_t>(net->rows);
+  float* p = net->scratch;
+  c.H.push_back(nullptr);
+  for (int l = 0; l < net->layers; ++l) {
+    c.H.push_back(p);
+    p += n * h;
+  }
+  c.D0 = p;
+  p += n * h;
+  c.D1 = p;
+  p += n * h;
+  c.y = p;
+  p += n;
+  c.dy = p;
+  p += n;
+  c.part = p;
+  p += SPLITS * std::max(h * h, h * 64);
+  c.lpart = p;
+  p += LB;
+  c.loss = p;
+  return c;
+}
+
+// y = net(X) for n <= net->rows rows; hidden activations kept in scratch
+int forward(ri_mlp* net, const float* X, long n, float* y, hipStream_t s) {
+  Scr c = carve(net);
+  const float* in = X;
+  int fin = net->d_in;
+  for (int l = 0; l <= net->layers; ++l) {
+    float *W, *b;
+    int fi, fo;
+    layer_ptrs(net, net->params, l, W, b, fi, fo);
+    GemmF32 g{};
+    g.M = n;
+    g.N = fo;
+    g.K = fi;
+    g.A = in;
+    g.sam = fin;
+    g.sak = 1;
+    g.B = W;
+    g.sbk = fo;
+    g.sbn = 1;
+    g.bias = b;
+    g.alpha = 1.f;
+    g.split_stride = 0;
+    if (l < net->layers) {
+      g.C = c.H[l + 1];
+      g.ldc = fo;
+      g.act = 1;
+    } else {
+      g.C = y;
+      g.ldc = 1;
+      g.act = 0;
+    }
+    RI_TRY(gemm(g, 1, s));
+    in = c.H[l + 1];
+    fin = fo;
+  }
+  return RI_OK;
+}
+
+// grad (device) and loss (device scalar in scratch) for the batch
+int gradient(ri_mlp* net, const float* X, const float* Y, long n, float* grad, hipStream_t s) {
+  RI_TRY(forward(net, X, n, carve(net).y, s));
+  Scr c = carve(net);
+  mse_stage1<<<LB, 256, 0, s>>>(c.y, Y, n, c.dy, c.lpart);
+  mse_stage2<<<1, 256, 0, s>>>(c.lpart, n, c.loss);
+  RI_TRY(check_launch("mse"));
+  // delta of the output layer: c.dy [n][1]
+  const float* delta = c.dy;
+  int dcols = 1;
+  float* dbuf[2] = {c.D0, c.D1};
+  int flip = 0;
+  const long splits = std::max(1L, std::min(static_cast<long>(SPLITS), n / 256));
+  for (int l = net->layers; l >= 0; --l) {
+    float *W, *b, *gW, *gb;
+    int fi, fo;
+    layer_ptrs(net, net->params, l, W, b, fi, fo);
+    layer_ptrs(net, grad, l, gW, gb, fi, fo);
+    const float* Hin = l > 0 ? c.H[l] : X;
+    // gW = Hin^T delta  (K = batch, deterministic split-K)
+    GemmF32 g{};
+    g.M = fi;
+    g.N = fo;
+    g.K = n;
+    g.A = Hin;
+    g.sam = 1;
+    g.sak = fi;
+    g.B = delta;
+    g.sbk = dcols;
+    g.sbn = 1;
+    g.C = c.part;
+    g.ldc = fo;
+    g.bias = nullptr;
+    g.act = 0;
+    g.alpha = 1.f;
+    g.split_stride = static_cast<long>(fi) * fo;
+    RI_TRY(gemm(g, static_cast<int>(splits), s));
+    sum_splits<<<nblk(static_cast<long>(fi) * fo), 256, 0, s>>>(c.part, static_cast<int>(splits),
+                                                                 static_cast<long>(fi) * fo, static_cast<long>(fi) * fo, gW);
+    RI_TRY(check_launch("sum_splits"));
+    // gb = column sums of delta
+    const long rper = (n + splits - 1) / splits;
+    colsum_partial<<<dim3((fo + 255) / 256, splits), 256, 0, s>>>(delta, n, fo, rper, c.part);
+    sum_splits<<<nblk(fo), 256, 0, s>>>(c.part, static_cast<int>(splits), fo, fo, gb);
+    RI_TRY(check_launch("bias grad"));
+    if (l == 0) break;
+    // dH = delta W^T ; delta_prev = dH * (1 - H^2)
+    float* dH = dbuf[flip];
+    flip ^= 1;
+    GemmF32 d{};
+    d.M = n;
+    d.N = fi;
+    d.K = fo;
+    d.A = delta;
+    d.sam = dcols;
+    d.sak = 1;
+    d.B = W;
+    d.sbk = 1;
+    d.sbn = fo;
+    d.C = dH;
+    d.ldc = fi;
+    d.bias = nullptr;
+    d.act = 0;
+    d.alpha = 1.f;
+    d.split_stride = 0;
+    RI_TRY(gemm(d, 1, s));
+    tanh_back<<<nblk(n * fi), 256, 0, s>>>(c.H[l], dH, n * fi);
+    RI_TRY(check_launch("tanh_back"));
+    delta = dH;
+    dcols = fi;
+  }
+  return RI_OK;
+}
+
+int check_net(const ri_mlp* net, const char* where) {
+  if (!net || !net->params) {
+    set_error("%s: null network", where);
+    return RI_E_ARG;
+  }
+  return RI_OK;
+}
+
+}  // namespace mlp
+}  // namespace ri
+
+using namespace ri;
+
+extern "C" {
+
+ri_mlp* ri_mlp_create(int d_in, int hidden, int layers) {
+  clear_error();
+  if (d_in <= 0 || hidden <= 0 || layers <= 0 || d_in > 4096 || hidden > 4096 || layers > 16) {
+    set_error("ri_mlp_create: invalid sizes");
+    return nullptr;
+  }
+  ri_mlp* net = new (std::nothrow) ri_mlp();
+  if (!net) return nullptr;
+  net->d_in = d_in;
+  net->hidden = hidden;
+  net->layers = layers;
+  size_t n = 0;
+  int in = d_in;
+  for (int l = 0; l <= layers; ++l) {
+    const int out = l < layers ? hidden : 1;
+    n += static_cast<size_t>(in) * out + out;
+    in = out;
+  }
+  net->nparams = n;
+  net->mean.assign(d_in, 0.f);
+  net->stdv.assign(d_in, 1.f);
+  float* p = nullptr;
+  if (hipMalloc(&p, 4 * n * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("ri_mlp_create: out of device memory");
+    delete net;
+    return nullptr;
+  }
+  if (hipMemset(p, 0, 4 * n * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(p);
+    delete net;
+    return nullptr;
+  }
+  net->params = p;
+  net->grad = p + n;
+  net->m = p + 2 * n;
+  net->v = p + 3 * n;
+  return net;
+}
+
+void ri_mlp_destroy(ri_mlp* net) {
+  if (!net) return;
+  if (net->scratch) (void)hipFree(net->scratch);
+  if (net->params) (void)hipFree(net->params);
+  delete net;
+}
+
+size_t ri_mlp_num_params(const ri_mlp* net) { return net ? net->nparams : 0; }
+
+int ri_mlp_set_params(ri_mlp* net, const float* params_host) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_set_params"));
+  if (!params_host) {
+    set_error("ri_mlp_set_params: null pointer");
+    return RI_E_ARG;
+  }
+  RI_HIP(hipMemcpy(net->params, params_host, net->nparams * sizeof(float), hipMemcpyHostToDevice));
+  RI_HIP(hipMemset(net->m, 0, 2 * net->nparams * sizeof(float)));
+  net->step = 0;
+  return RI_OK;
+}
+
+int ri_mlp_get_params(const ri_mlp* net, float* params_host) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_get_params"));
+  if (!params_host) {
+    set_error("ri_mlp_get_params: null pointer");
+    return RI_E_ARG;
+  }
+  RI_HIP(hipMemcpy(params_host, net->params, net->nparams * sizeof(float), hipMemcpyDeviceToHost));
+  return RI_OK;
+}
+
+int ri_mlp_set_scaling(ri_mlp* net, const float* mean, const float* std, float y_scale) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_set_scaling"));
+  if (!mean || !std || !(y_scale > 0.f)) {
+    set_error("ri_mlp_set_scaling: invalid argument");
+    return RI_E_ARG;
+  }
+  for (int k = 0; k < net->d_in; ++k)
+    if (!(std[k] > 0.f)) {
+      set_error("ri_mlp_set_scaling: std must be positive");
+      return RI_E_ARG;
+    }
+  net->mean.assign(mean, mean + net->d_in);
+  net->stdv.assign(std, std + net->d_in);
+  net->y_scale = y_scale;
+  return RI_OK;
+}
+
+int ri_mlp_get_scaling(const ri_mlp* net, float* mean, float* std, float* y_scale) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_get_scaling"));
+  if (mean) memcpy(mean, net->mean.data(), net->d_in * sizeof(float));
+  if (std) memcpy(std, net->stdv.data(), net->d_in * sizeof(float));
+  if (y_scale) *y_scale = net->y_scale;
+  return RI_OK;
+}
+
+int ri_mlp_forward(ri_mlp* net, const float* X, long n, float* y, void* stream) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_forward"));
+  if (!X || !y || n <= 0) {
+    set_error("ri_mlp_forward: invalid argument");
+    return RI_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long chunk = 1L << 20;
+  RI_TRY(mlp::reserve(net, std::min(n, chunk), s));
+  for (long r0 = 0; r0 < n; r0 += chunk) {
+    const long nn = std::min(chunk, n - r0);
+    RI_TRY(mlp::forward(net, X + r0 * net->d_in, nn, y + r0, s));
+  }
+  return RI_OK;
+}
+
+int ri_mlp_gradient(ri_mlp* net, const float* X, const float* Y, long n, float* grad, float* loss_host, void* stream) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_gradient"));
+  if (!X || !Y || n <= 0 || n > (1L << 24)) {
+    set_error("ri_mlp_gradient: invalid argument");
+    return RI_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RI_TRY(mlp::reserve(net, n, s));
+  float* g = grad ? grad : net->grad;
+  RI_TRY(mlp::gradient(net, X, Y, n, g, s));
+  if (loss_host) {
+    RI_HIP(hipMemcpyAsync(loss_host, mlp::carve(net).loss, sizeof(float), hipMemcpyDeviceToHost, s));
+    RI_HIP(hipStreamSynchronize(s));
+  }
+  return RI_OK;
+}
+
+int ri_mlp_train_step(ri_mlp* net, const float* X, const float* Y, long n, float lr, float* loss_host, void* stream) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_train_step"));
+  if (!X || !Y || n <= 0 || n > (1L << 24) || !(lr > 0.f)) {
+    set_error("ri_mlp_train_step: invalid argument");
+    return RI_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RI_TRY(mlp::reserve(net, n, s));
+  RI_TRY(mlp::gradient(net, X, Y, n, net->grad, s));
+  net->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, static_cast<float>(net->step)), c2 = 1.f - powf(b2, static_cast<float>(net->step));
+  mlp::adam_kernel<<<mlp::nblk(net->nparams), 256, 0, s>>>(net->params, net->grad, net->m, net->v, net->nparams, lr,
+                                                            b1, b2, 1e-8f, c1, c2);
+  RI_TRY(check_launch("adam_kernel"));
+  if (loss_host) {
+    RI_HIP(hipMemcpyAsync(loss_host, mlp::carve(net).loss, sizeof(float), hipMemcpyDeviceToHost, s));
+    RI_HIP(hipStreamSynchronize(s));
+  }
+  return RI_OK;
+}
+
+int ri_mlp_features(const ri_system* sys, const double* t2_mp2, float* X, void* stream) {
+  clear_error();
+  RI_TRY(cc::check_system(sys, "ri_mlp_features"));
+  if (!t2_mp2 || !X) {
+    set_error("ri_mlp_features: null pointer");
+    return RI_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long n = static_cast<long>(sys->o) * sys->o * sys->v * sys->v;
+  void* buf = nullptr;
+  RI_TRY(dev_alloc(&buf, static_cast<size_t>(n) * sizeof(double), s));
+  double* gov = static_cast<double*>(buf);
+  int rc = cc::ovov_integrals(sys, gov, s);
+  if (rc == RI_OK) {
+    mlp::Norm nm{};
+    nm.on = 0;
+    mlp::features_kernel<<<mlp::nblk(n), 256, 0, s>>>(gov, sys->eps, t2_mp2, sys->o, sys->v, 0, n, nm, X);
+    rc = check_launch("features_kernel");
+  }
+  dev_free(buf, s);
+  return rc;
+}
+
+int ri_mlp_guess(ri_mlp* net, const ri_system* sys, double* t1, double* t2, void* stream) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_guess"));
+  RI_TRY(cc::check_system(sys, "ri_mlp_guess"));
+  if (!t1 || !t2 || net->d_in != mlp::NF) {
+    set_error("ri_mlp_guess: null amplitudes or a network without %d inputs", mlp::NF);
+    return RI_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int o = sys->o, v = sys->v;
+  const long n = static_cast<long>(o) * o * v * v;
+  const long chunk = std::min(n, 1L << 20);
+  // gov [o][v][o][v], an unmodified copy of the MP2 t2 (features read it), X and y of a chunk
+  const size_t gbytes = round_up(static_cast<size_t>(n) * sizeof(double), 256);
+  void* buf = nullptr;
+  RI_TRY(dev_alloc(&buf, 2 * gbytes + static_cast<size_t>(chunk) * (mlp::NF + 1) * sizeof(float), s));
+  double* gov = static_cast<double*>(buf);
+  double* t2m = reinterpret_cast<double*>(static_cast<char*>(buf) + gbytes);
+  float* X = reinterpret_cast<float*>(static_cast<char*>(buf) + 2 * gbytes);
+  float* y = X + chunk * mlp::NF;
+  mlp::Norm nm{};
+  nm.on = 1;
+  for (int k = 0; k < mlp::NF; ++k) {
+    nm.mean[k] = net->mean[k];
+    nm.inv_std[k] = 1.f / net->stdv[k];
+  }
+  int rc = cc::mp2_with_integrals(sys, gov, t1, t2m, s);
+  if (rc == RI_OK) rc = check_hip(hipMemcpyAsync(t2, t2m, static_cast<size_t>(n) * sizeof(double),
+                                                 hipMemcpyDeviceToDevice, s), "ri_mlp_guess copy");
+  if (rc == RI_OK) rc = mlp::reserve(net, chunk, s);
+  for (long r0 = 0; r0 < n && rc == RI_OK; r0 += chunk) {
+    const long nn = std::min(chunk, n - r0);
+    mlp::features_kernel<<<mlp::nblk(nn), 256, 0, s>>>(gov, sys->eps, t2m, o, v, r0, nn, nm, X);
+    if ((rc = check_launch("features_kernel"))) break;
+    if ((rc = mlp::forward(net, X, nn, y, s))) break;
+    mlp::add_correction<<<mlp::nblk(nn), 256, 0, s>>>(t2, r0, nn, y, net->y_scale);
+    rc = check_launch("add_correction");
+  }
+  if (rc == RI_OK) rc = cc::symmetrize_pairs(t2, o, v, s);
+  dev_free(buf, s);
+  return rc;
+}
+
+int ri_mlp_save(const ri_mlp* net, const char* path) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_save"));
+  if (!path) {
+    set_error("ri_mlp_save: null path");
+    return RI_E_ARG;
+  }
+  std::vector<float> p(net->nparams);
+  RI_HIP(hipMemcpy(p.data(), net->params, p.size() * sizeof(float), hipMemcpyDeviceToHost));
+  FILE* f = fopen(path, "wb");
+  if (!f) {
+    set_error("ri_mlp_save: cannot open %s", path);
+    return RI_E_ARG;
+  }
+  const int hdr[4] = {0x504c4d52, net->d_in, net->hidden, net->layers};  // "RMLP"
+  bool ok = fwrite(hdr, sizeof(hdr), 1, f) == 1 && fwrite(net->mean.data(), sizeof(float), net->d_in, f) == (size_t)net->d_in &&
+            fwrite(net->stdv.data(), sizeof(float), net->d_in, f) == (size_t)net->d_in &&
+            fwrite(&net->y_scale, sizeof(float), 1, f) == 1 && fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
+  ok = (fclose(f) == 0) && ok;
+  if (!ok) {
+    set_error("ri_mlp_save: write to %s failed", path);
+    return RI_E_ARG;
+  }
+  return RI_OK;
+}
+
+ri_mlp* ri_mlp_load(const char* path) {
+  clear_error();
+  if (!path) {
+    set_error("ri_mlp_load: null path");
+    return nullptr;
+  }
+  FILE* f = fopen(path, "rb");
+  if (!f) {
+    set_error("ri_mlp_load: cannot open %s", path);
+    return nullptr;
+  }
+  int hdr[4];
+  ri_mlp* net = nullptr;
+  if (fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x504c4d52) net = ri_mlp_create(hdr[1], hdr[2], hdr[3]);
+  bool ok = net != nullptr;
+  if (ok) {
+    std::vector<float> mean(net->d_in), stdv(net->d_in), p(net->nparams);
+    float ys = 0.f;
+    ok = fread(mean.data(), sizeof(float), net->d_in, f) == (size_t)net->d_in &&
+         fread(stdv.data(), sizeof(float), net->d_in, f) == (size_t)net->d_in && fread(&ys, sizeof(float), 1, f) == 1 &&
+         fread(p.data(), sizeof(float), p.size(), f) == p.size();
+    ok = ok && ri_mlp_set_scaling(net, mean.data(), stdv.data(), ys) == RI_OK && ri_mlp_set_params(net, p.data()) == RI_OK;
+  }
+  fclose(f);
+  if (!ok) {
+    ri_mlp_destroy(net);
+    set_error("ri_mlp_load: %s is not a valid network file", path);
+    return nullptr;
+  }
+  return net;
+}
+
+}  // extern "C"

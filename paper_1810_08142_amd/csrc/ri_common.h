@@ -55,6 +55,16 @@ class ProfScope {
 int ppl_strided(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
                 int precision, hipStream_t s);
 
+namespace cc {
+int check_system(const ri_system* sys, const char* where);
+// (ia|jb) as gov [o][v][o][v] (caller buffer).
+int ovov_integrals(const ri_system* sys, double* gov, hipStream_t s);
+// MP2 amplitudes with the (ia|jb) integrals kept in gov [o][v][o][v] (caller buffer).
+int mp2_with_integrals(const ri_system* sys, double* gov, double* t1, double* t2, hipStream_t s);
+// t2 <- (t2 + t2^T) / 2 with t2^T[i][j][a][b] = t2[j][i][b][a]
+int symmetrize_pairs(double* t2, int o, int v, hipStream_t s);
+}  // namespace cc
+
 // Byte ranges [a, a+na) and [b, b+nb) overlap?
 inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);

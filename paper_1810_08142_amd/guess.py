@@ -1,0 +1,187 @@
+"""Train and evaluate the learned starting guess for the doubles amplitudes.
+
+Training data: seeded synthetic systems (o ~ U{4..12}, v ~ U{40..120}, naux = 3v,
+Naux-normalised factor scale) converged by the GPU CCSD solver from the MP2 guess;
+each system contributes a random sample of its amplitudes with features from the
+MP2 quantities and the target t2_CCSD - t2_MP2.  The network is trained with the
+library's own forward/backward/Adam kernels and saved with ri_mlp_save.
+
+  python -m paper_1810_08142_amd.guess train --out model.bin [--systems 256]
+  python -m paper_1810_08142_amd.guess evaluate --model model.bin [--config c5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def build_dataset(shapes, per_system: int, seed: int, scale="naux", tol: float = 1e-8, log=None):
+    """(X [N][8] float32, Y [N] float32, info) from converged systems."""
+    import torch
+
+    from . import ccsd, mlp
+    from .synthetic import draw_system
+    rng = np.random.default_rng(seed)
+    Xs, Ys = [], []
+    iters = []
+    t0 = time.perf_counter()
+    for k, (o, v, naux, sd) in enumerate(shapes):
+        s = draw_system(o, v, naux, seed=sd, scale=scale)
+        B = torch.from_numpy(s.B).to("cuda")
+        eps = torch.from_numpy(s.eps).to("cuda")
+        t2m, _ = ccsd.mp2_guess(B, eps, o)
+        X = mlp.features(B, eps, o, t2m)
+        _, t2, rep = ccsd.solve(B, eps, o, tol=tol, tol_energy=tol * 0.1, max_iter=200)
+        if not rep.converged:
+            if log:
+                log(f"  system {k} (o={o} v={v}) did not converge; skipped")
+            continue
+        iters.append(rep.iterations)
+        d = (t2 - t2m).reshape(-1)
+        n = d.numel()
+        idx = rng.choice(n, size=min(per_system, n), replace=False)
+        idx_t = torch.from_numpy(np.sort(idx)).to("cuda")
+        Xs.append(X.index_select(0, idx_t).cpu().numpy())
+        Ys.append(d.index_select(0, idx_t).cpu().numpy().astype(np.float32))
+        if log and (k % 32 == 0 or k == len(shapes) - 1):
+            log(f"  system {k + 1}/{len(shapes)} o={o} v={v}: {rep.iterations} iterations, "
+                f"{time.perf_counter() - t0:.1f} s elapsed")
+    info = dict(systems=len(Xs), mean_iterations=float(np.mean(iters)) if iters else None,
+                seconds=time.perf_counter() - t0)
+    return np.concatenate(Xs), np.concatenate(Ys), info
+
+
+def train(X, Y, hidden=256, layers=2, epochs=30, batch=4096, lr=5e-4, seed=0, holdout=0.05, log=None):
+    """Fit the network to (X, Y) with the GPU kernels; returns (net, history).
+
+    Features are standardised and the target divided by its standard deviation
+    (both stored in the network); a held-out fraction measures the fit."""
+    import torch
+
+    from . import mlp
+    rng = np.random.default_rng(seed + 1)
+    perm0 = rng.permutation(X.shape[0])
+    nho = int(holdout * X.shape[0])
+    ho, tr = perm0[:nho], perm0[nho:]
+    mean = X[tr].mean(axis=0).astype(np.float32)
+    std = X[tr].std(axis=0).astype(np.float32)
+    std[std <= 0] = 1.0
+    y_scale = float(Y[tr].std()) or 1.0
+    Xn = ((X - mean) / std).astype(np.float32)
+    Yn = (Y / y_scale).astype(np.float32)
+    net = mlp.Net(X.shape[1], hidden, layers)
+    net.set_params(mlp.init_params(X.shape[1], hidden, layers, seed))
+    net.set_scaling(mean, std, y_scale)
+    Xho = torch.from_numpy(Xn[ho]).to("cuda")
+    Yho = Yn[ho]
+    n = tr.size
+    steps = max(1, n // batch)
+    total = epochs * steps
+    warm = max(1, total // 20)
+    hist = []
+    it = 0
+    for ep in range(epochs):
+        perm = tr[rng.permutation(n)]
+        Xd = torch.from_numpy(Xn[perm]).to("cuda")
+        Yd = torch.from_numpy(Yn[perm]).to("cuda")
+        for st in range(steps):
+            # linear warm-up, then cosine decay
+            lr_t = lr * min(1.0, (it + 1) / warm) * 0.5 * (1.0 + np.cos(np.pi * it / total))
+            net.train_step(Xd[st * batch:(st + 1) * batch], Yd[st * batch:(st + 1) * batch], lr_t, want_loss=False)
+            it += 1
+        yho = net.forward(Xho).cpu().numpy()
+        ho_loss = float(np.mean((yho - Yho) ** 2))
+        hist.append(ho_loss)
+        if log:
+            log(f"  epoch {ep + 1}/{epochs}: held-out loss {ho_loss:.4e} (target variance 1)")
+    return net, hist
+
+
+def evaluate(net, config="c5", scale="naux", precision="fp64", tol=1e-8, log=None):
+    """Iterations and wall time to convergence from the MP2 and the learned guess."""
+    import torch
+
+    from . import ccsd
+    from .synthetic import CONFIGS, draw_system
+    c = CONFIGS[config]
+    s = draw_system(c["o"], c["v"], c["naux"], seed=c["seed"], scale=scale)
+    B = torch.from_numpy(s.B).to("cuda")
+    eps = torch.from_numpy(s.eps).to("cuda")
+    torch.cuda.synchronize()
+    out = dict(config=config, o=s.o, v=s.v, naux=s.naux, seed=s.seed, scale=s.scale, precision=precision, tol=tol)
+    # MP2 guess
+    _, t2a, ra = ccsd.solve(B, eps, s.o, tol=tol, tol_energy=tol * 0.1, ppl_precision=precision)
+    torch.cuda.synchronize()
+    # learned guess
+    t0 = time.perf_counter()
+    t1g, t2g = net.guess(B, eps, s.o)
+    torch.cuda.synchronize()
+    t_guess = time.perf_counter() - t0
+    t2m, _ = ccsd.mp2_guess(B, eps, s.o)
+    err_mp2 = float((t2m - t2a).abs().max())
+    err_net = float((t2g - t2a).abs().max())
+    rms_mp2 = float((t2m - t2a).pow(2).mean().sqrt())
+    rms_net = float((t2g - t2a).pow(2).mean().sqrt())
+    del t2m
+    _, t2b, rb = ccsd.solve(B, eps, s.o, t1=t1g, t2=t2g, tol=tol, tol_energy=tol * 0.1, ppl_precision=precision)
+    out["initial_error"] = dict(mp2_max=err_mp2, learned_max=err_net, mp2_rms=rms_mp2, learned_rms=rms_net)
+    out["mp2_guess"] = dict(iterations=ra.iterations, seconds=ra.seconds_total, e_corr=ra.e_corr,
+                            converged=ra.converged)
+    out["learned_guess"] = dict(iterations=rb.iterations, seconds=rb.seconds_total + t_guess,
+                                seconds_guess=t_guess, e_corr=rb.e_corr, converged=rb.converged)
+    out["delta_e_corr"] = rb.e_corr - ra.e_corr
+    out["max_abs_delta_t2"] = float((t2a - t2b).abs().max())
+    out["speedup"] = ra.seconds_total / (rb.seconds_total + t_guess)
+    if log:
+        log(json.dumps(out))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--out", required=True)
+    t.add_argument("--systems", type=int, default=256)
+    t.add_argument("--per-system", type=int, default=8192)
+    t.add_argument("--epochs", type=int, default=30)
+    t.add_argument("--batch", type=int, default=4096)
+    t.add_argument("--lr", type=float, default=5e-4)
+    t.add_argument("--evaluate", default="")
+    e = sub.add_parser("evaluate")
+    e.add_argument("--model", required=True)
+    e.add_argument("--config", default="c5")
+    e.add_argument("--precision", default="fp64")
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    from . import mlp
+    from .synthetic import training_shapes
+    if args.cmd == "train":
+        shapes = training_shapes()[:args.systems]
+        log(f"[guess] building dataset from {len(shapes)} systems")
+        X, Y, info = build_dataset(shapes, args.per_system, seed=12345, log=log)
+        log(f"[guess] {X.shape[0]} samples from {info['systems']} systems in {info['seconds']:.1f} s")
+        t0 = time.perf_counter()
+        net, hist = train(X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+        t_train = time.perf_counter() - t0
+        net.save(args.out)
+        res = dict(samples=int(X.shape[0]), dataset=info, train_seconds=t_train, heldout_loss_first=hist[0],
+                   heldout_loss_final=hist[-1], out=args.out)
+        if args.evaluate:
+            res["evaluation"] = evaluate(net, args.evaluate, log=log)
+        print(json.dumps(res), flush=True)
+    else:
+        net = mlp.Net.load(args.model)
+        print(json.dumps(evaluate(net, args.config, precision=args.precision, log=log)), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

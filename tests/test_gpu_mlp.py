@@ -1,0 +1,116 @@
+"""Learned-guess network kernels on the GPU against the FP64 CPU oracle.
+
+GPU arithmetic is FP32 (sums of at most 256 products per unit and of the batch
+for gradients); tolerance 1e-4 relative to the largest value."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from gpu_util import dev, host
+from oracle import ccsd as oc
+from oracle import mlp as om
+from paper_1810_08142_amd.synthetic import draw_matrix, draw_system
+
+pytestmark = pytest.mark.gpu
+
+
+def _net(d_in=8, hidden=256, layers=2, seed=1):
+    from paper_1810_08142_amd import mlp
+    net = mlp.Net(d_in, hidden, layers)
+    theta = mlp.init_params(d_in, hidden, layers, seed)
+    theta[-1] = 0.3  # a non-zero output bias
+    net.set_params(theta)
+    return net, theta.astype(np.float64)
+
+
+@pytest.mark.parametrize("hidden,layers,n", [(16, 1, 37), (256, 2, 1000), (64, 3, 513)])
+def test_forward_and_gradient_match_oracle(hidden, layers, n):
+    import torch
+    net, theta = _net(8, hidden, layers, seed=hidden + layers)
+    X = draw_matrix((n, 8), 5).astype(np.float32)
+    Y = (0.5 * draw_matrix(n, 6)).astype(np.float32)
+    y = host(net.forward(dev(X)))
+    yr, _ = om.forward(theta, X.astype(np.float64), 8, hidden, layers)
+    assert np.abs(y - yr).max() <= 1e-4 * max(1.0, np.abs(yr).max())
+    loss, g = net.gradient(dev(X), dev(Y))
+    Lr, gr = om.gradient(theta, X.astype(np.float64), Y.astype(np.float64), 8, hidden, layers)
+    assert abs(loss - Lr) <= 1e-4 * Lr
+    g = host(g)
+    assert np.abs(g - gr).max() <= 1e-4 * np.abs(gr).max()
+
+
+def test_adam_step_matches_oracle():
+    net, theta = _net(8, 32, 2, seed=9)
+    n = 300
+    X = draw_matrix((n, 8), 7).astype(np.float32)
+    Y = draw_matrix(n, 8).astype(np.float32)
+    lr = 1e-2
+    loss = net.train_step(dev(X), dev(Y), lr)
+    new = net.get_params().astype(np.float64)
+    L, g = om.gradient(theta, X.astype(np.float64), Y.astype(np.float64), 8, 32, 2)
+    ref, _, _ = om.adam_step(theta, g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    assert abs(loss - L) <= 1e-4 * L
+    clear = np.abs(g) > 1e-3 * np.abs(g).max()  # the first step is lr*sign(g): skip g ~ 0
+    assert np.abs(new - ref)[clear].max() <= 1e-5
+
+
+def test_features_match_oracle():
+    from paper_1810_08142_amd import mlp
+    o, v, naux = 3, 13, 20
+    s = draw_system(o, v, naux, seed=950)
+    _, t2, _ = oc.mp2(s.B, s.eps, o)
+    X = host(mlp.features(dev(s.B), dev(s.eps), o, dev(t2)))
+    ref = om.features(s.B, s.eps, o, t2).reshape(-1, om.N_FEATURES)
+    scale = np.abs(ref).max(axis=0)
+    assert np.all(np.abs(X - ref) <= 1e-6 * scale + 1e-12)
+
+
+def test_zero_network_gives_mp2_and_correction_is_applied():
+    from paper_1810_08142_amd import mlp
+    o, v, naux = 2, 11, 15
+    s = draw_system(o, v, naux, seed=960)
+    B, eps = dev(s.B), dev(s.eps)
+    net = mlp.Net()
+    net.set_scaling(np.zeros(8), np.ones(8), 1.0)
+    t1, t2 = net.guess(B, eps, o)
+    _, t2r, _ = oc.mp2(s.B, s.eps, o)
+    assert np.abs(host(t1)).max() == 0.0
+    assert np.abs(host(t2) - t2r).max() <= 1e-15 * np.abs(t2r).max()
+    theta = np.zeros(net.num_params, dtype=np.float32)
+    theta[-1] = 0.5  # output bias only: every amplitude moves by y_scale * 0.5
+    net.set_params(theta)
+    net.set_scaling(np.zeros(8), np.ones(8), 0.01)
+    _, t2c = net.guess(B, eps, o)
+    shift = 0.5 * float(np.float32(0.01))  # the scale is stored in FP32
+    assert float(np.abs(host(t2c) - (t2r + shift)).max()) <= 1e-12
+
+
+def test_save_load_roundtrip():
+    from paper_1810_08142_amd import mlp
+    net, theta = _net(8, 64, 2, seed=3)
+    net.set_scaling(np.arange(8), np.arange(1, 9), 0.25)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "net.bin")
+        net.save(path)
+        other = mlp.Net.load(path)
+    assert other.num_params == net.num_params
+    assert np.array_equal(other.get_params(), net.get_params())
+    m, sd, ys = other.get_scaling()
+    assert np.array_equal(m, np.arange(8, dtype=np.float32)) and ys == np.float32(0.25)
+
+
+def test_training_reduces_loss():
+    import torch
+    from paper_1810_08142_amd import mlp
+    net, _ = _net(8, 64, 2, seed=4)
+    n = 4096
+    X = draw_matrix((n, 8), 11).astype(np.float32)
+    Y = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2]).astype(np.float32)
+    Xd, Yd = dev(X), dev(Y)
+    first = net.train_step(Xd, Yd, 3e-3)
+    for _ in range(300):
+        last = net.train_step(Xd, Yd, 3e-3, want_loss=False)
+    last = net.train_step(Xd, Yd, 3e-3)
+    assert last < 0.1 * first
