@@ -34,7 +34,7 @@ def log(*a):
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("ppl.hip", "ri_common.h"):
+    for name in ("ppl.hip", "ppl_bf16.hip", "ppl_shared.h", "ri_common.h"):
         with open(os.path.join(ROOT, "paper_1810_08142_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "bf16x3"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -122,6 +124,15 @@ def main():
     flops = ppl.flops(o, v, naux)
     stream = torch.cuda.current_stream()
 
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_calibration} MiB device to device for counter calibration")
+        del src, dst
     for w in range(args.warmup):
         ppl.ppl(B_vv, tau, R, precision=args.precision)
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
