@@ -165,7 +165,7 @@ struct Ctx {
          *Gk = nullptr, *xq = nullptr, *ones = nullptr, *part = nullptr, *scal = nullptr, *tvec = nullptr,
          *om = nullptr, *hist = nullptr;
   int m = 0;  // DIIS slots
-  TableArena arena;
+  GemmArena arena;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
   Ctx(const ri_system* sys, hipStream_t st)

@@ -25,8 +25,11 @@ struct GemmDesc {
   long a_batch, b_batch, c_batch;
 };
 
-size_t table_longs(const GemmDesc& g);
-int run(const GemmDesc& g, int batch, long* tab, hipStream_t s);
+// Doubles of scratch the split-k form of a contraction wants (0: not split).
+size_t scratch_doubles(const GemmDesc& g, int batch);
+// Launches the contraction; it is split over k when `scratch` holds at least
+// scratch_doubles(g, batch) doubles, else it runs in one pass.
+int run(const GemmDesc& g, int batch, double* scratch, size_t scratch_len, hipStream_t s);
 
 }  // namespace gemm
 
@@ -48,13 +51,13 @@ struct Tensor {
   }
 };
 
-// Scratch for contraction offset tables (grown on demand, stream-ordered).
-struct TableArena {
-  long* p = nullptr;
+// Scratch for split-k partial products (grown on demand, stream-ordered).
+struct GemmArena {
+  double* p = nullptr;
   size_t cap = 0;
   hipStream_t s = nullptr;
-  int reserve(size_t longs);
-  ~TableArena();
+  int reserve(size_t doubles);
+  ~GemmArena();
 };
 
 // out[c_idx] = alpha * sum A[a_idx] B[b_idx] + beta * out, described einsum-style,
@@ -63,7 +66,7 @@ struct TableArena {
 // dimension).  Letters are merged into the contraction's index levels when their
 // strides allow; at most 2 output-row, 2 output-column and 3 summed levels remain.
 int einsum(const char* spec, double alpha, const Tensor& A, const Tensor& B, double beta, const Tensor& out,
-           TableArena& arena, hipStream_t s);
+           GemmArena& arena, hipStream_t s);
 
 // out = alpha * permute(in) + beta * out, with spec like "kiac->aikc" (in -> out letters).
 int axpby_perm(const char* spec, double alpha, const Tensor& in, double beta, const Tensor& out, hipStream_t s);

@@ -4,9 +4,11 @@
 //
 // where m, n and k are compound indices: m = (m1, m2), n = (n1, n2),
 // k = (k1, k2, k3), each level with its own stride, so a contraction over a
-// permuted index pair of a 4-index tensor needs no transposed copy.  The index
-// decomposition is turned into offset tables once per call (gemm_tables), and
-// the MFMA kernel gathers operand tiles through them into LDS.
+// permuted index pair of a 4-index tensor needs no transposed copy.  Each thread
+// walks its k indices with incremental counters (no tables, no divisions in the
+// loop).  Contractions with few output tiles and a long k range are split over k
+// into partial products that a second kernel sums in a fixed order, so the result
+// does not depend on scheduling.
 #include "gemm.h"
 
 namespace ri {
@@ -16,51 +18,50 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, KC = 16;
 
-__global__ void gemm_tables(GemmDesc g, long* tab) {
-  long* amoff = tab;
-  long* cmoff = amoff + g.M;
-  long* bnoff = cmoff + g.M;
-  long* cnoff = bnoff + g.N;
-  long* akoff = cnoff + g.N;
-  long* bkoff = akoff + g.K;
-  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx < g.M) {
-    const long m1 = idx / g.M2, m2 = idx % g.M2;
-    amoff[idx] = m1 * g.am1 + m2 * g.am2;
-    cmoff[idx] = m1 * g.cm1 + m2 * g.cm2;
-  }
-  if (idx < g.N) {
-    const long n1 = idx / g.N2, n2 = idx % g.N2;
-    bnoff[idx] = n1 * g.bn1 + n2 * g.bn2;
-    cnoff[idx] = n1 * g.cn1 + n2 * g.cn2;
-  }
-  if (idx < g.K) {
-    const long k3 = idx % g.K3, r = idx / g.K3;
-    const long k2 = r % g.K2, k1 = r / g.K2;
-    akoff[idx] = k1 * g.ak1 + k2 * g.ak2 + k3 * g.ak3;
-    bkoff[idx] = k1 * g.bk1 + k2 * g.bk2 + k3 * g.bk3;
+// One operand element stream: position k (decomposed as (k1, k2, k3)) and its
+// offset, advanced by KC per chunk.
+struct KWalk {
+  long k, k2, k3, off;
+};
+
+__device__ inline KWalk kwalk_init(long k, long K2, long K3, long s1, long s2, long s3) {
+  KWalk w;
+  w.k = k;
+  w.k3 = k % K3;
+  const long r = k / K3;
+  w.k2 = r % K2;
+  w.off = (r / K2) * s1 + w.k2 * s2 + w.k3 * s3;
+  return w;
+}
+
+__device__ inline void kwalk_step(KWalk& w, long K2, long K3, long s1, long s2, long s3) {
+  w.k += KC;
+  w.k3 += KC;
+  w.off += KC * s3;
+  while (w.k3 >= K3) {
+    w.k3 -= K3;
+    w.off += s2 - K3 * s3;
+    if (++w.k2 >= K2) {
+      w.k2 = 0;
+      w.off += s1 - K2 * s2;
+    }
   }
 }
 
 // tile 64 x 64, 4 waves in a 2 x 2 arrangement, each wave 32 x 32 (2 x 2 MFMA tiles).
 // a_kfast / b_kfast choose which index consecutive threads walk when loading.
-// grid (ceil(N/64), ceil(M/64), batch), block 256
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, const long* __restrict__ tab,
-                                                       int a_kfast, int b_kfast) {
+// grid (ceil(N/64), ceil(M/64), batch * splits); with splits > 1 the raw products of
+// k range z go to part + z * M * N (row-major [M][N]).
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, int a_kfast, int b_kfast, int splits, long kper,
+                                                       double* __restrict__ part) {
   __shared__ double sA[2][KC][BM + 1];
   __shared__ double sB[2][KC][BN + 1];
-  const long* amoff = tab;
-  const long* cmoff = amoff + g.M;
-  const long* bnoff = cmoff + g.M;
-  const long* cnoff = bnoff + g.N;
-  const long* akoff = cnoff + g.N;
-  const long* bkoff = akoff + g.K;
-
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const long bm = static_cast<long>(blockIdx.y) * BM, bn = static_cast<long>(blockIdx.x) * BN;
-  const double* A = g.a + blockIdx.z * g.a_batch;
-  const double* B = g.b + blockIdx.z * g.b_batch;
-  double* C = g.c + blockIdx.z * g.c_batch;
+  const int zb = blockIdx.z / splits, zs = blockIdx.z % splits;
+  const double* A = g.a + zb * g.a_batch;
+  const double* B = g.b + zb * g.b_batch;
+  const long k_lo = zs * kper, k_hi = std::min(g.K, k_lo + kper);
 
   // each thread loads one row (m or n) and four k of each operand per chunk
   const int am = a_kfast ? (t >> 2) : (t & 63);
@@ -69,9 +70,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, const long* _
   const int bnn = b_kfast ? (t >> 2) : (t & 63);
   const int bk = b_kfast ? ((t & 3) << 2) : (t >> 6);
   const int bkstep = b_kfast ? 1 : 4;
-  const bool arow = bm + am < g.M, brow = bn + bnn < g.N;
-  const long aoff = arow ? amoff[bm + am] : 0;
-  const long boff = brow ? bnoff[bn + bnn] : 0;
+  const long mrow = bm + am, ncol = bn + bnn;
+  const bool arow = mrow < g.M, brow = ncol < g.N;
+  const long aoff = arow ? (mrow / g.M2) * g.am1 + (mrow % g.M2) * g.am2 : 0;
+  const long boff = brow ? (ncol / g.N2) * g.bn1 + (ncol % g.N2) * g.bn2 : 0;
+  KWalk wa[4], wb[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    wa[r] = kwalk_init(k_lo + ak + r * akstep, g.K2, g.K3, g.ak1, g.ak2, g.ak3);
+    wb[r] = kwalk_init(k_lo + bk + r * bkstep, g.K2, g.K3, g.bk1, g.bk2, g.bk3);
+  }
 
   double ra[4], rb[4];
   double4_t acc[2][2];
@@ -81,12 +89,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, const long* _
     for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
   const int l16 = lane & 15, kq = lane >> 4;
-  const long nchunks = (g.K + KC - 1) / KC;
+  const long nchunks = k_hi > k_lo ? (k_hi - k_lo + KC - 1) / KC : 0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const long ka = ak + r * akstep, kb = bk + r * bkstep;
-    ra[r] = (arow && ka < g.K) ? A[aoff + akoff[ka]] : 0.0;
-    rb[r] = (brow && kb < g.K) ? B[boff + bkoff[kb]] : 0.0;
+    ra[r] = (arow && wa[r].k < k_hi) ? A[aoff + wa[r].off] : 0.0;
+    rb[r] = (brow && wb[r].k < k_hi) ? B[boff + wb[r].off] : 0.0;
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -98,12 +105,12 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, const long* _
     const int buf = ch & 1;
     const bool more = ch + 1 < nchunks;
     if (more) {
-      const long k0 = (ch + 1) * KC;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const long ka = k0 + ak + r * akstep, kb = k0 + bk + r * bkstep;
-        ra[r] = (arow && ka < g.K) ? A[aoff + akoff[ka]] : 0.0;
-        rb[r] = (brow && kb < g.K) ? B[boff + bkoff[kb]] : 0.0;
+        kwalk_step(wa[r], g.K2, g.K3, g.ak1, g.ak2, g.ak3);
+        kwalk_step(wb[r], g.K2, g.K3, g.bk1, g.bk2, g.bk3);
+        ra[r] = (arow && wa[r].k < k_hi) ? A[aoff + wa[r].off] : 0.0;
+        rb[r] = (brow && wb[r].k < k_hi) ? B[boff + wb[r].off] : 0.0;
       }
     }
 #pragma unroll
@@ -129,41 +136,78 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, const long* _
     __syncthreads();
   }
   // D[4r + lane/16][lane%16] in element r
+  double* C = g.c + zb * g.c_batch;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const long n = bn + wn + 16 * j + l16;
       if (n >= g.N) continue;
-      const long cn = cnoff[n];
+      const long cn = (n / g.N2) * g.cn1 + (n % g.N2) * g.cn2;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const long m = bm + wm + 16 * i + 4 * r + kq;
         if (m >= g.M) continue;
-        double* p = C + cmoff[m] + cn;
-        const double val = g.alpha * acc[i][j][r];
-        *p = g.beta == 0.0 ? val : val + g.beta * *p;
+        if (splits > 1) {
+          part[(zs * g.M + m) * g.N + n] = acc[i][j][r];
+        } else {
+          double* p = C + (m / g.M2) * g.cm1 + (m % g.M2) * g.cm2 + cn;
+          const double val = g.alpha * acc[i][j][r];
+          *p = g.beta == 0.0 ? val : val + g.beta * *p;
+        }
       }
     }
 }
 
-size_t table_longs(const GemmDesc& g) { return 2 * static_cast<size_t>(g.M) + 2 * g.N + 2 * g.K; }
+// C(m, n) = alpha * sum_z part[z][m][n] + beta * C(m, n), z in order
+__global__ void split_reduce(GemmDesc g, int splits, const double* __restrict__ part) {
+  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= g.M * g.N) return;
+  const long m = idx / g.N, n = idx % g.N;
+  double acc = 0.0;
+  for (int z = 0; z < splits; ++z) acc += part[z * g.M * g.N + idx];
+  double* p = g.c + (m / g.M2) * g.cm1 + (m % g.M2) * g.cm2 + (n / g.N2) * g.cn1 + (n % g.N2) * g.cn2;
+  const double val = g.alpha * acc;
+  *p = g.beta == 0.0 ? val : val + g.beta * *p;
+}
 
-int run(const GemmDesc& g, int batch, long* tab, hipStream_t s) {
+// Split over k when the output has too few tiles to fill the chip: aim at about
+// 2048 workgroups, each split at least 32 chunks of k, partials at most 2^26 doubles.
+size_t scratch_doubles(const GemmDesc& g, int batch) {
+  const long tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  if (batch > 1 || tiles >= 1024) return 0;
+  long splits = std::min<long>(1024, 2048 / tiles);
+  splits = std::min(splits, g.K / (32 * KC));
+  splits = std::min(splits, (1L << 26) / (g.M * g.N));
+  if (splits < 2) return 0;
+  return static_cast<size_t>(splits) * g.M * g.N;
+}
+
+int run(const GemmDesc& g, int batch, double* scratch, size_t scratch_len, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || batch <= 0) return RI_OK;
   if (g.K <= 0) {
     set_error("gemm: K must be positive");
     return RI_E_ARG;
   }
-  const long mx = std::max(std::max(g.M, g.N), g.K);
-  gemm_tables<<<static_cast<unsigned>((mx + 255) / 256), 256, 0, s>>>(g, tab);
-  RI_TRY(check_launch("gemm_tables"));
   // consecutive threads walk k when the innermost k stride is 1 and the m/n stride is not
   const int a_kfast = (g.ak3 == 1 && g.K3 >= 4 && g.am2 != 1) ? 1 : 0;
   const int b_kfast = (g.bk3 == 1 && g.K3 >= 4 && g.bn2 != 1) ? 1 : 0;
-  dim3 grid(static_cast<unsigned>((g.N + BN - 1) / BN), static_cast<unsigned>((g.M + BM - 1) / BM), batch);
-  gemm_f64_kernel<<<grid, 256, 0, s>>>(g, tab, a_kfast, b_kfast);
-  return check_launch("gemm_f64_kernel");
+  const size_t want = scratch_doubles(g, batch);
+  int splits = 1;
+  if (want > 0 && scratch && scratch_len >= want) splits = static_cast<int>(want / (static_cast<size_t>(g.M) * g.N));
+  // k range of each split, a whole number of chunks; trailing splits may be empty
+  // (they write zero partials)
+  const long kper = splits > 1 ? ((g.K + splits - 1) / splits + KC - 1) / KC * KC : g.K;
+  dim3 grid(static_cast<unsigned>((g.N + BN - 1) / BN), static_cast<unsigned>((g.M + BM - 1) / BM),
+            static_cast<unsigned>(batch * splits));
+  gemm_f64_kernel<<<grid, 256, 0, s>>>(g, a_kfast, b_kfast, splits, kper, scratch);
+  RI_TRY(check_launch("gemm_f64_kernel"));
+  if (splits > 1) {
+    const long n = g.M * g.N;
+    split_reduce<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(g, splits, scratch);
+    RI_TRY(check_launch("split_reduce"));
+  }
+  return RI_OK;
 }
 
 }  // namespace gemm

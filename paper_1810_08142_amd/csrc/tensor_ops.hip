@@ -7,20 +7,20 @@
 namespace ri {
 
 // ------------------------------------------------------------------ arena
-int TableArena::reserve(size_t longs) {
-  if (longs <= cap) return RI_OK;
+int GemmArena::reserve(size_t doubles) {
+  if (doubles <= cap) return RI_OK;
   if (p) dev_free(p, s);
   p = nullptr;
   cap = 0;
-  const size_t want = std::max(longs, static_cast<size_t>(1) << 16);
+  const size_t want = std::max(doubles, static_cast<size_t>(1) << 16);
   void* q = nullptr;
-  RI_TRY(dev_alloc(&q, want * sizeof(long), s));
-  p = static_cast<long*>(q);
+  RI_TRY(dev_alloc(&q, want * sizeof(double), s));
+  p = static_cast<double*>(q);
   cap = want;
   return RI_OK;
 }
 
-TableArena::~TableArena() {
+GemmArena::~GemmArena() {
   if (p) dev_free(p, s);
 }
 
@@ -70,7 +70,7 @@ std::vector<Level> merge(const std::vector<Level>& in) {
 }  // namespace
 
 int einsum(const char* spec, double alpha, const Tensor& A, const Tensor& B, double beta, const Tensor& C,
-           TableArena& arena, hipStream_t s) {
+           GemmArena& arena, hipStream_t s) {
   Spec sp;
   if (!parse(spec, sp) || sp.a.size() != A.dims.size() || sp.b.size() != B.dims.size() ||
       sp.c.size() != C.dims.size()) {
@@ -120,7 +120,18 @@ int einsum(const char* spec, double alpha, const Tensor& A, const Tensor& B, dou
     set_error("einsum '%s': needs at least one summed letter and at most one batch letter", spec);
     return RI_E_ARG;
   }
-  std::vector<Level> m = merge(mL), n = merge(nL), k = merge(kA);
+  // Row and column letters may be taken in any order: put the one with the
+  // smallest stride in the operand that is loaded along it innermost (coalesced
+  // loads), unless that leaves too many levels after merging.
+  auto by_stride = [](std::vector<Level> v, bool use_a) {
+    std::stable_sort(v.begin(), v.end(), [&](const Level& x, const Level& y) {
+      return use_a ? std::labs(x.sa) > std::labs(y.sa) : std::labs(x.sb) > std::labs(y.sb);
+    });
+    return merge(v);
+  };
+  std::vector<Level> m = by_stride(mL, true), n = by_stride(nL, false), k = merge(kA);
+  if (m.size() > 2) m = merge(mL);
+  if (n.size() > 2) n = merge(nL);
   if (k.size() > 3) k = merge(kB);
   if (m.size() > 2 || n.size() > 2 || k.size() > 3) {
     set_error("einsum '%s': too many index levels after merging (%zu, %zu, %zu)", spec, m.size(), n.size(), k.size());
@@ -158,8 +169,10 @@ int einsum(const char* spec, double alpha, const Tensor& A, const Tensor& B, dou
     g.c_batch = batch[0].sc;
   }
   arena.s = s;
-  RI_TRY(arena.reserve(gemm::table_longs(g)));
-  return gemm::run(g, nb, arena.p, s);
+  const size_t need = gemm::scratch_doubles(g, nb);
+  if (need) RI_TRY(arena.reserve(need));
+  ProfScope ps(s, spec, 2.0 * static_cast<double>(g.M) * g.N * g.K * nb);
+  return gemm::run(g, nb, arena.p, arena.cap, s);
 }
 
 // ------------------------------------------------------------------ permuted axpby
@@ -216,6 +229,7 @@ int axpby_perm(const char* spec, double alpha, const Tensor& in, double beta, co
     total *= out.dims[k];
   }
   if (total == 0) return RI_OK;
+  ProfScope ps(s, "axpby_perm", 0.0, 16.0 * total);
   axpby_perm_kernel<<<static_cast<unsigned>((total + 255) / 256), 256, 0, s>>>(d, alpha, in.p, beta,
                                                                               const_cast<double*>(out.p), total);
   return check_launch("axpby_perm_kernel");
