@@ -111,6 +111,9 @@ typedef struct ri_system {
 
 #define RI_GUESS_MP2 0  /* t1 = 0, t2 = (ia|jb) / D (iteration 0) */
 #define RI_GUESS_USER 1 /* start from the t1, t2 passed in */
+#define RI_GUESS_MLP 2  /* the MP2 guess corrected by the network opts->mlp (ri_mlp_guess) */
+
+typedef struct ri_mlp ri_mlp; /* learned starting guess, declared below */
 
 typedef struct ri_ccsd_opts {
   int max_iter;        /* iteration limit (default 100) */
@@ -119,18 +122,34 @@ typedef struct ri_ccsd_opts {
   int diis_size;       /* stored vectors, 2..16; < 2 disables DIIS (default 6) */
   int diis_start;      /* first iteration that extrapolates (default 2) */
   int ppl_precision;   /* RI_PREC_* of the ladder term (default RI_PREC_FP64) */
-  int guess;           /* RI_GUESS_MP2 or RI_GUESS_USER */
+  int guess;           /* RI_GUESS_MP2, RI_GUESS_USER or RI_GUESS_MLP */
   int verbose;         /* one line per iteration on stderr */
+  /* Mixed-precision ladder only: once max |Omega| <= polish_residual, every later
+   * residual uses the FP64 ladder, and convergence is only declared on an FP64
+   * residual (0 disables; default 0). */
+  double polish_residual;
+  /* Mixed-precision ladder only: evaluate max |Omega| of the returned amplitudes
+   * once more with the FP64 ladder into rep->residual_inf_fp64 (default 0). */
+  int check_fp64;
+  ri_mlp* mlp; /* network for RI_GUESS_MLP (default NULL) */
 } ri_ccsd_opts;
 
 typedef struct ri_ccsd_report {
   double e_corr;       /* correlation energy of the returned amplitudes (Hartree) */
-  double e_mp2;        /* MP2 energy of the guess (NaN for RI_GUESS_USER) */
+  double e_mp2;        /* MP2 energy of the guess (NaN unless RI_GUESS_MP2) */
   double residual_inf; /* max |Omega| at the last residual evaluation */
   int iterations;      /* residual evaluations minus one */
   int converged;
-  double seconds_total; /* wall time of the call, guess included */
+  double seconds_total; /* wall time of the call, guess included, check_fp64 excluded */
   double seconds_ppl;   /* GPU time of the ladder term */
+  double residual_rms;  /* root mean square of Omega at the last residual evaluation */
+  /* max |Omega| of the returned amplitudes with the FP64 ladder: equals
+   * residual_inf when the last residual used it (converged FP64 or polished runs),
+   * NaN when not evaluated */
+  double residual_inf_fp64;
+  int polish_iteration; /* first iteration whose residual used the FP64 ladder after a
+                           mixed start (-1: none) */
+  double seconds_guess; /* wall time until the guess and its energy were ready */
 } ri_ccsd_report;
 
 /* Fills the defaults listed above. */
@@ -169,8 +188,6 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
  * beta2 0.999, eps 1e-8).  The handle owns its device memory; calls that take a
  * stream enqueue on it; a handle must not be used from two streams at once.
  * ------------------------------------------------------------------------ */
-typedef struct ri_mlp ri_mlp;
-
 /* New network with zero parameters (NULL on failure, see ri_last_error_msg). */
 ri_mlp* ri_mlp_create(int d_in, int hidden, int layers);
 void ri_mlp_destroy(ri_mlp* net);

@@ -29,13 +29,15 @@ class RISystem(_c.Structure):
 class RICcsdOpts(_c.Structure):
     _fields_ = [("max_iter", _c.c_int), ("tol_residual", _c.c_double), ("tol_energy", _c.c_double),
                 ("diis_size", _c.c_int), ("diis_start", _c.c_int), ("ppl_precision", _c.c_int),
-                ("guess", _c.c_int), ("verbose", _c.c_int)]
+                ("guess", _c.c_int), ("verbose", _c.c_int), ("polish_residual", _c.c_double),
+                ("check_fp64", _c.c_int), ("mlp", _c.c_void_p)]
 
 
 class RICcsdReport(_c.Structure):
     _fields_ = [("e_corr", _c.c_double), ("e_mp2", _c.c_double), ("residual_inf", _c.c_double),
                 ("iterations", _c.c_int), ("converged", _c.c_int), ("seconds_total", _c.c_double),
-                ("seconds_ppl", _c.c_double)]
+                ("seconds_ppl", _c.c_double), ("residual_rms", _c.c_double), ("residual_inf_fp64", _c.c_double),
+                ("polish_iteration", _c.c_int), ("seconds_guess", _c.c_double)]
 
 
 _sysp = _c.POINTER(RISystem)

@@ -68,11 +68,19 @@ class Report:
     seconds_total: float
     seconds_ppl: float
     status: int
+    residual_rms: float = float("nan")
+    residual_inf_fp64: float = float("nan")
+    polish_iteration: int = -1
+    seconds_guess: float = float("nan")
 
 
 def solve(B, eps, o, t1=None, t2=None, max_iter=100, tol=1e-10, tol_energy=1e-10, diis_size=6,
-          diis_start=2, ppl_precision="fp64", verbose=False, stream=None, raise_on_noconv=False):
-    """Jacobi + DIIS from the MP2 guess (or from t1/t2 when given).
+          diis_start=2, ppl_precision="fp64", verbose=False, stream=None, raise_on_noconv=False,
+          polish_residual=0.0, check_fp64=False, mlp=None):
+    """Jacobi + DIIS from the MP2 guess, from t1/t2 when given, or from the learned
+    guess of `mlp` (a paper_1810_08142_amd.mlp.Net).  With a mixed-precision ladder,
+    `polish_residual` > 0 switches the ladder to FP64 once max |Omega| falls below it,
+    and `check_fp64` evaluates the FP64 residual of the final amplitudes.
     Returns (t1, t2, Report); t1/t2 passed in are overwritten."""
     sy = _system(B, eps, o)
     v = sy.v
@@ -82,8 +90,14 @@ def solve(B, eps, o, t1=None, t2=None, max_iter=100, tol=1e-10, tol_energy=1e-10
     op.max_iter, op.tol_residual, op.tol_energy = max_iter, tol, tol_energy
     op.diis_size, op.diis_start, op.ppl_precision = diis_size, diis_start, _prec(ppl_precision)
     op.verbose = 1 if verbose else 0
+    op.polish_residual = float(polish_residual)
+    op.check_fp64 = 1 if check_fp64 else 0
+    if mlp is not None and t2 is not None:
+        raise ValueError("pass either a network or starting amplitudes, not both")
     if t2 is None:
-        op.guess = 0
+        op.guess = 2 if mlp is not None else 0
+        if mlp is not None:
+            op.mlp = mlp.handle
         t1 = torch.empty((o, v), dtype=torch.float64, device=B.device)
         t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=B.device)
     else:
@@ -98,5 +112,6 @@ def solve(B, eps, o, t1=None, t2=None, max_iter=100, tol=1e-10, tol_energy=1e-10
     if rc not in (0, 5) or (rc == 5 and raise_on_noconv):
         _lib.check(rc, "ri_ccsd_iterate")
     r = Report(rep.e_corr, rep.e_mp2, rep.residual_inf, rep.iterations, bool(rep.converged), rep.seconds_total,
-               rep.seconds_ppl, rc)
+               rep.seconds_ppl, rc, rep.residual_rms, rep.residual_inf_fp64, rep.polish_iteration,
+               rep.seconds_guess)
     return t1, t2, r

@@ -1,8 +1,14 @@
 """Command-line runs of the GPU RI-CCSD solver on the synthetic workloads.
 
   python -m paper_1810_08142_amd.cli ccsd --config c5 [--scale verbatim|naux] [--precision fp64|bf16x3]
+                                        [--polish 1e-6] [--check-fp64] [--model net.bin]
+  python -m paper_1810_08142_amd.cli ttc --config c3 --scale naux [--polish 1e-6]
 
-Prints one JSON line with the report (energy, iterations, timings, scale used).
+`ccsd` prints one JSON line with the report (energy, iterations, timings, scale
+used).  `ttc` (time to converged E_corr) solves one system three times -- FP64
+ladder, mixed ladder, mixed ladder with FP64 polish -- and prints one JSON line per
+run with its E_corr error against the FP64 run and the FP64 residual of its final
+amplitudes.
 """
 from __future__ import annotations
 
@@ -24,7 +30,21 @@ def main(argv=None):
     c.add_argument("--tol-energy", type=float, default=1e-9)
     c.add_argument("--diis", type=int, default=6)
     c.add_argument("--verbose", action="store_true")
+    c.add_argument("--polish", type=float, default=0.0)
+    c.add_argument("--check-fp64", action="store_true")
+    c.add_argument("--model", default="")
+    t = sub.add_parser("ttc")
+    t.add_argument("--config", default="c3")
+    t.add_argument("--scale", default="naux")
+    t.add_argument("--mixed", default="bf16x3")
+    t.add_argument("--polish", type=float, default=1e-6)
+    t.add_argument("--max-iter", type=int, default=100)
+    t.add_argument("--tol", type=float, default=1e-8)
+    t.add_argument("--tol-energy", type=float, default=1e-9)
+    t.add_argument("--verbose", action="store_true")
     args = ap.parse_args(argv)
+    if args.cmd == "ttc":
+        return _ttc(args)
 
     import torch
 
@@ -38,18 +58,55 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     from ._lib import RIError
+    net = None
+    if args.model:
+        from .mlp import Net
+        net = Net.load(args.model)
     try:
         t1, t2, rep = ccsd.solve(B, eps, s.o, max_iter=args.max_iter, tol=args.tol, tol_energy=args.tol_energy,
-                                 diis_size=args.diis, ppl_precision=args.precision, verbose=args.verbose)
+                                 diis_size=args.diis, ppl_precision=args.precision, verbose=args.verbose,
+                                 polish_residual=args.polish, check_fp64=args.check_fp64, mlp=net)
     except RIError as e:
         print(json.dumps(dict(config=args.config, scale=s.scale, precision=args.precision, error=str(e))), flush=True)
         return 4
     out = dict(config=args.config, o=s.o, v=s.v, naux=s.naux, seed=s.seed, scale=s.scale, precision=args.precision,
                e_corr=rep.e_corr, e_mp2=rep.e_mp2, iterations=rep.iterations, converged=rep.converged,
-               residual_inf=rep.residual_inf, seconds_total=rep.seconds_total, seconds_ppl=rep.seconds_ppl,
-               seconds_generate=t_gen, max_abs_t2=float(t2.abs().max()))
+               residual_inf=rep.residual_inf, residual_rms=rep.residual_rms,
+               residual_inf_fp64=rep.residual_inf_fp64, polish_iteration=rep.polish_iteration,
+               seconds_total=rep.seconds_total, seconds_ppl=rep.seconds_ppl, seconds_guess=rep.seconds_guess,
+               seconds_generate=t_gen, guess="mlp" if net is not None else "mp2", max_abs_t2=float(t2.abs().max()))
     print(json.dumps(out), flush=True)
     return 0 if rep.converged else 3
+
+
+def _ttc(args):
+    import torch
+
+    from . import ccsd
+    from .synthetic import CONFIGS, draw_system
+    cfg = CONFIGS[args.config]
+    s = draw_system(cfg["o"], cfg["v"], cfg["naux"], seed=cfg["seed"], scale=args.scale)
+    B = torch.from_numpy(s.B).to("cuda")
+    eps = torch.from_numpy(s.eps).to("cuda")
+    torch.cuda.synchronize()
+    runs = [("fp64", "fp64", 0.0), ("mixed", args.mixed, 0.0), ("mixed+polish", args.mixed, args.polish)]
+    ref = None
+    rc = 0
+    for name, prec, pol in runs:
+        _, _, rep = ccsd.solve(B, eps, s.o, max_iter=args.max_iter, tol=args.tol, tol_energy=args.tol_energy,
+                               ppl_precision=prec, polish_residual=pol, check_fp64=True, verbose=args.verbose)
+        if ref is None:
+            ref = rep
+        out = dict(config=args.config, o=s.o, v=s.v, naux=s.naux, seed=s.seed, scale=s.scale, run=name,
+                   precision=prec, polish_residual=pol, tol=args.tol, tol_energy=args.tol_energy,
+                   converged=rep.converged, iterations=rep.iterations, polish_iteration=rep.polish_iteration,
+                   e_corr=rep.e_corr, delta_e_vs_fp64=rep.e_corr - ref.e_corr,
+                   residual_inf=rep.residual_inf, residual_inf_fp64=rep.residual_inf_fp64,
+                   seconds_total=rep.seconds_total, seconds_ppl=rep.seconds_ppl,
+                   speedup_vs_fp64=ref.seconds_total / rep.seconds_total)
+        print(json.dumps(out), flush=True)
+        rc = rc or (0 if rep.converged else 3)
+    return rc
 
 
 if __name__ == "__main__":

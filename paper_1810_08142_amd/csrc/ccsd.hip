@@ -422,6 +422,9 @@ void ri_ccsd_default_opts(ri_ccsd_opts* op) {
   op->ppl_precision = RI_PREC_FP64;
   op->guess = RI_GUESS_MP2;
   op->verbose = 0;
+  op->polish_residual = 0.0;
+  op->check_fp64 = 0;
+  op->mlp = nullptr;
 }
 
 int ri_mp2_guess(const ri_system* sys, double* t1, double* t2, double* e_mp2, void* stream) {
@@ -489,11 +492,14 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
   ri_ccsd_opts op;
   if (opts) op = *opts;
   else ri_ccsd_default_opts(&op);
-  if (op.max_iter < 0 || op.diis_size > 16 || op.guess < 0 || op.guess > 1) {
-    set_error("ri_ccsd_iterate: invalid options (max_iter %d, diis_size %d, guess %d)", op.max_iter, op.diis_size,
-              op.guess);
+  if (op.max_iter < 0 || op.diis_size > 16 || op.guess < RI_GUESS_MP2 || op.guess > RI_GUESS_MLP ||
+      !(op.polish_residual >= 0.0) || (op.guess == RI_GUESS_MLP && !op.mlp)) {
+    set_error("ri_ccsd_iterate: invalid options (max_iter %d, diis_size %d, guess %d, polish %g, mlp %p)",
+              op.max_iter, op.diis_size, op.guess, op.polish_residual, static_cast<void*>(op.mlp));
     return RI_E_ARG;
   }
+  const bool mixed = op.ppl_precision != RI_PREC_FP64;
+  const bool polish = mixed && op.polish_residual > 0.0;
   const int slots = op.diis_size >= 2 ? op.diis_size : 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
   cc::Ctx c(sys, s);
@@ -504,6 +510,8 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
   double* tv2 = c.tvec + nov;
   if (op.guess == RI_GUESS_MP2) {
     RI_TRY(c.mp2(tv1, tv2));
+  } else if (op.guess == RI_GUESS_MLP) {
+    RI_TRY(ri_mlp_guess(op.mlp, sys, tv1, tv2, stream));
   } else {
     RI_HIP(hipMemcpyAsync(tv1, t1, sizeof(double) * nov, hipMemcpyDeviceToDevice, s));
     RI_HIP(hipMemcpyAsync(tv2, t2, sizeof(double) * c.noovv, hipMemcpyDeviceToDevice, s));
@@ -515,7 +523,9 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
   RI_TRY(c.read_scalars(hostv, 1));
   double e = hostv[0];
   const double e_mp2 = op.guess == RI_GUESS_MP2 ? e : NAN;
-  double e_prev = NAN, rinf = INFINITY;
+  const double sec_guess = std::chrono::duration<double>(clk::now() - t_start).count();
+  double e_prev = NAN, rinf = INFINITY, rrms = INFINITY;
+  int prec = op.ppl_precision, polish_it = -1;
   bool conv = false;
   int it = 0;
   double ms_ppl_total = 0.0;
@@ -525,20 +535,31 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
   int status = RI_OK;
   for (it = 0; it < op.max_iter; ++it) {
     float ms_ppl = 0.f;
-    RI_TRY(c.residual(tv1, tv2, c.om, c.om + nov, op.ppl_precision, &ms_ppl));
+    RI_TRY(c.residual(tv1, tv2, c.om, c.om + nov, prec, &ms_ppl));
     ms_ppl_total += ms_ppl;
     RI_TRY(max_abs(c.om, nt, c.part, c.scal, s));
-    RI_TRY(c.read_scalars(hostv, 1));
+    RI_TRY(dot(c.om, c.om, nt, c.part, c.scal + 1, s));
+    RI_TRY(c.read_scalars(hostv, 2));
     rinf = hostv[0];
-    if (op.verbose) fprintf(stderr, "[ccsd] iter %3d  E = %.12f  |Omega|inf = %.3e  ladder %.1f ms\n", it, e, rinf, ms_ppl);
+    rrms = std::sqrt(hostv[1] / static_cast<double>(nt));
+    if (op.verbose)
+      fprintf(stderr, "[ccsd] iter %3d  E = %.12f  |Omega|inf = %.3e  ladder %s %.1f ms\n", it, e, rinf,
+              prec == RI_PREC_FP64 ? "fp64" : "mixed", ms_ppl);
     if (!std::isfinite(rinf) || !std::isfinite(e) || rinf > 1e8) {
       set_error("ri_ccsd_iterate: non-finite or divergent residual at iteration %d", it);
       status = RI_E_NUMERIC;
       break;
     }
-    if (it > 0 && rinf <= op.tol_residual && std::fabs(e - e_prev) <= op.tol_energy) {
+    const bool on_fp64 = prec == RI_PREC_FP64;
+    if (it > 0 && rinf <= op.tol_residual && std::fabs(e - e_prev) <= op.tol_energy && (on_fp64 || !polish)) {
       conv = true;
       break;
+    }
+    // switch to the FP64 ladder for the remaining residuals (the step below still
+    // uses this mixed residual)
+    if (polish && !on_fp64 && rinf <= op.polish_residual) {
+      prec = RI_PREC_FP64;
+      polish_it = it + 1;
     }
     // Jacobi step into the next history slot
     const int slot = next_slot;
@@ -595,16 +616,34 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
     e_prev = e;
     e = hostv[0];
   }
+  const double sec_total = std::chrono::duration<double>(clk::now() - t_start).count();
+  // max |Omega| of the returned amplitudes with the FP64 ladder
+  double rinf64 = NAN;
+  if (status == RI_OK) {
+    if (conv && prec == RI_PREC_FP64) {
+      rinf64 = rinf;
+    } else if (mixed && op.check_fp64) {
+      float ms = 0.f;
+      RI_TRY(c.residual(tv1, tv2, c.om, c.om + nov, RI_PREC_FP64, &ms));
+      RI_TRY(max_abs(c.om, nt, c.part, c.scal, s));
+      RI_TRY(c.read_scalars(hostv, 1));
+      rinf64 = hostv[0];
+    }
+  }
   RI_HIP(hipMemcpyAsync(t1, tv1, sizeof(double) * nov, hipMemcpyDeviceToDevice, s));
   RI_HIP(hipMemcpyAsync(t2, tv2, sizeof(double) * c.noovv, hipMemcpyDeviceToDevice, s));
   RI_HIP(hipStreamSynchronize(s));
   if (rep) {
+    rep->residual_rms = rrms;
+    rep->residual_inf_fp64 = rinf64;
+    rep->polish_iteration = polish_it;
+    rep->seconds_guess = sec_guess;
     rep->e_corr = e;
     rep->e_mp2 = e_mp2;
     rep->residual_inf = rinf;
     rep->iterations = it;
     rep->converged = conv ? 1 : 0;
-    rep->seconds_total = std::chrono::duration<double>(clk::now() - t_start).count();
+    rep->seconds_total = sec_total;
     rep->seconds_ppl = ms_ppl_total * 1e-3;
   }
   if (status != RI_OK) return status;

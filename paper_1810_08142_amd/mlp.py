@@ -88,6 +88,11 @@ class Net:
                    "ri_mlp_train_step")
         return loss.value if want_loss else None
 
+    @property
+    def handle(self):
+        """The ri_mlp handle (an integer address) for the C ABI."""
+        return self._h
+
     def guess(self, B: torch.Tensor, eps: torch.Tensor, o: int, stream=None):
         """(t1, t2): the MP2 amplitudes corrected by the network, FP64."""
         sy = _system(B, eps, o)

@@ -107,3 +107,53 @@ def test_numeric_failure_is_reported():
     with pytest.raises(_lib.RIError) as e:
         _cc().solve(dev(s.B), dev(s.eps), o, t1=dev(np.zeros((o, v))), t2=dev(t2))
     assert e.value.status == 6
+
+
+def test_report_rms_matches_final_residual():
+    import torch
+    o, v, naux = 3, 20, 40
+    s = draw_system(o, v, naux, seed=850)
+    B, eps = dev(s.B), dev(s.eps)
+    t1, t2, rep = _cc().solve(B, eps, o, tol=1e-9, tol_energy=1e-10)
+    assert rep.converged and np.isfinite(rep.seconds_guess) and 0 < rep.seconds_guess <= rep.seconds_total
+    om1, om2 = _cc().residual(B, eps, o, t1, t2)
+    om = torch.cat([om1.reshape(-1), om2.reshape(-1)])
+    # the last residual of a converged run is the residual of the returned amplitudes
+    assert float(om.abs().max()) == rep.residual_inf
+    assert abs(float(om.pow(2).mean().sqrt()) - rep.residual_rms) <= 1e-12 * rep.residual_rms
+    assert rep.residual_inf_fp64 == rep.residual_inf and rep.polish_iteration == -1
+
+
+def test_mixed_ladder_with_fp64_polish_reaches_fp64_fixed_point():
+    c = CONFIGS["c1"]
+    o = c["o"]
+    s = draw_system(o, c["v"], c["naux"], seed=c["seed"])
+    B, eps = dev(s.B), dev(s.eps)
+    _, t2a, r64 = _cc().solve(B, eps, o, tol=1e-10, tol_energy=1e-10)
+    _, t2b, rp = _cc().solve(B, eps, o, ppl_precision="bf16x3", polish_residual=1e-6, tol=1e-10, tol_energy=1e-10)
+    print("fp64", r64, "polished", rp, flush=True)
+    assert rp.converged and rp.polish_iteration > 0
+    assert rp.residual_inf_fp64 == rp.residual_inf <= 1e-10
+    assert abs(rp.e_corr - r64.e_corr) <= 1e-10
+    assert float((t2a - t2b).abs().max()) <= 1e-9
+    # without polish the FP64 residual of the mixed fixed point is evaluated on request
+    _, _, rm = _cc().solve(B, eps, o, ppl_precision="bf16x3", tol=1e-8, tol_energy=1e-9, check_fp64=True)
+    assert rm.converged and rm.polish_iteration == -1
+    assert np.isfinite(rm.residual_inf_fp64) and rm.residual_inf_fp64 <= 1e-6
+    assert abs(rm.e_corr - r64.e_corr) <= 1e-6
+
+
+def test_learned_guess_option_matches_guess_then_user_start():
+    from paper_1810_08142_amd import mlp
+    o, v, naux = 3, 20, 40
+    s = draw_system(o, v, naux, seed=860)
+    B, eps = dev(s.B), dev(s.eps)
+    net = mlp.Net()
+    net.set_params(mlp.init_params(8, 256, 2, seed=5))
+    net.set_scaling(np.zeros(8), np.ones(8), 1e-4)
+    g1, g2 = net.guess(B, eps, o)
+    _, ta, ra = _cc().solve(B, eps, o, t1=g1, t2=g2, tol=1e-10, tol_energy=1e-11)
+    _, tb, rb = _cc().solve(B, eps, o, mlp=net, tol=1e-10, tol_energy=1e-11)
+    assert ra.converged and rb.converged and ra.iterations == rb.iterations
+    assert ra.e_corr == rb.e_corr and bool((ta == tb).all())
+    assert np.isnan(rb.e_mp2)
