@@ -227,7 +227,9 @@ __global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W
   constexpr int BN = 16 * NTW;
   __shared__ double sA[2][KC][64];
   __shared__ double sB[2][KC][BN];
-  const long n0 = static_cast<long>(blockIdx.x) * BN, m0 = static_cast<long>(blockIdx.y) * 64;
+  unsigned tx, ty;
+  xcd_tile(tx, ty);
+  const long n0 = static_cast<long>(tx) * BN, m0 = static_cast<long>(ty) * 64;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 
   // staging offsets (computed once; the chunk loop adds k0 * row stride)
@@ -398,8 +400,8 @@ static bool make_plan(int o, int v, int naux, Plan& p) {
   p.K = p.nbp * 256;
   p.po = o * (o + 1) / 2;
   p.pm = o * (o - 1) / 2;
-  pick_ntw(p.po, 10, p.ntw_p, p.NP);
-  pick_ntw(p.pm, 10, p.ntw_m, p.NM);
+  pick_ntw(p.po, 10, 64, p.ntw_p, p.NP);
+  pick_ntw(p.pm, 10, 64, p.ntw_m, p.NM);
   if (p.pm == 0) p.NM = 0;
   const int nw = p.pm > 0 ? 2 : 1;
   const long budget = env_long("RI_PPL_W_BYTES", 16L << 30);

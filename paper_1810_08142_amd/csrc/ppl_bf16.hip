@@ -285,7 +285,9 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
   constexpr int ARUNS = CBM * 2 * 4, BRUNS = BN * 2 * 4;
   __shared__ u32x4_t sA[2 * ARUNS];
   __shared__ u32x4_t sB[2 * BRUNS];
-  const long n0 = static_cast<long>(blockIdx.x) * BN, m0 = static_cast<long>(blockIdx.y) * CBM;
+  unsigned tx, ty;
+  xcd_tile(tx, ty);
+  const long n0 = static_cast<long>(tx) * BN, m0 = static_cast<long>(ty) * CBM;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 
   // staging: A 1024 runs (4 per thread), B 8*BN runs (ceil(BN/32) per thread)
@@ -402,8 +404,8 @@ static bool make_mplan(int o, int v, int naux, MPlan& p) {
   p.K = p.nbp * 256;
   p.po = o * (o + 1) / 2;
   p.pm = o * (o - 1) / 2;
-  pick_ntw(p.po, 9, p.ntw_p, p.NP);
-  pick_ntw(p.pm, 9, p.ntw_m, p.NM);
+  pick_ntw(p.po, 9, CBM, p.ntw_p, p.NP);
+  pick_ntw(p.pm, 9, CBM, p.ntw_m, p.NM);
   if (p.pm == 0) p.NM = 0;
   const int nw = p.pm > 0 ? 2 : 1;
   const long budget = env_long("RI_PPL_W_BYTES", 16L << 30);

@@ -24,18 +24,38 @@ __host__ __device__ inline void tri_decode(long p, int& x, int& y) {
 
 // Contraction column tiling: ntw 16-wide column tiles per workgroup tile (1..maxw),
 // chosen to minimise the padded column count (ties: wider tiles).
-inline void pick_ntw(int ncols, int maxw, int& ntw, int& padded) {
+// Columns per contraction tile (ntw tiles of 16) for ncols output columns.  A tile
+// of `rows` rows and 16*ntw columns loads rows + 16*ntw operand rows per k step, so
+// the traffic of the whole contraction goes as padded * (rows/16 + ntw) / ntw: wide
+// tiles pay for some zero padding.
+inline void pick_ntw(int ncols, int maxw, int rows, int& ntw, int& padded) {
   const int n16 = std::max(1, (ncols + NG - 1) / NG);
+  const double r = rows / 16.0;
   ntw = 1;
-  int best = 1 << 30;
+  double best = 1e300;
+  int best_pad = n16;
   for (int c = 1; c <= maxw; ++c) {
     const int p = (n16 + c - 1) / c * c;
-    if (p < best || (p == best && c > ntw)) {
-      best = p;
+    const double cost = p * (r + c) / c;
+    if (cost < best * (1.0 - 1e-12)) {
+      best = cost;
       ntw = c;
+      best_pad = p;
     }
   }
-  padded = best * NG;
+  padded = best_pad * NG;
+}
+
+// Workgroups are dispatched to the eight XCDs round-robin by linear id; this maps
+// the linear id so that each XCD works through a contiguous run of tiles (x
+// fastest), so tiles that share operand rows share one L2.
+__device__ inline void xcd_tile(unsigned& tx, unsigned& ty) {
+  const unsigned gx = gridDim.x, nwg = gridDim.x * gridDim.y;
+  const unsigned id = blockIdx.x + gx * blockIdx.y;
+  const unsigned per = nwg / 8, rem = nwg % 8, x = id % 8, j = id / 8;
+  const unsigned tile = (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + j;
+  tx = tile % gx;
+  ty = tile / gx;
 }
 
 inline long env_long(const char* name, long dflt) {
