@@ -181,8 +181,10 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
 /* ------------------------------------------------------------------------
  * Learned starting guess (not in the paper; an addition on top of the MP2 guess).
  * A fully connected network -- `layers` tanh hidden layers of `hidden` units and
- * one linear output -- maps 8 per-amplitude MP2 features to a correction of the
- * MP2 doubles amplitudes: t2 = t2_MP2 + y_scale * net((x - mean) / std).
+ * one linear output -- maps 8 per-amplitude MP2 features to a relative correction
+ * of the MP2 doubles amplitudes: t2 = t2_MP2 * (1 + y_scale * net((x - mean) / std)).
+ * (A relative correction keeps the guess error proportional to each amplitude, so
+ * the small amplitudes stay as accurate as MP2 makes them.)
  * Parameters form one FP32 vector W1 [d_in][h], b1 [h], ..., W_out [h][1], b_out [1].
  * Training runs on the GPU (loss: batch mean of (y - Y)^2, Adam with beta1 0.9,
  * beta2 0.999, eps 1e-8).  The handle owns its device memory; calls that take a
@@ -213,8 +215,8 @@ int ri_mlp_train_step(ri_mlp* net, const float* X, const float* Y, long n, float
  * MP2 t2 and the (ia|jb) integrals of sys: t2_ijab, t2_ijba, (ia|jb), (ib|ja),
  * e_i + e_j - e_a - e_b, (e_a - e_b)^2, (e_i - e_j)^2, sqrt((ia|ia)(jb|jb)). */
 int ri_mlp_features(const ri_system* sys, const double* t2_mp2, float* X, void* stream);
-/* Learned guess: t1 = 0, t2 = t2_MP2 + correction, pair-symmetrised (FP64 outputs).
- * The network must have 8 inputs. */
+/* Learned guess: t1 = 0, t2 = t2_MP2 * (1 + y_scale * net), pair-symmetrised (FP64
+ * outputs).  The network must have 8 inputs. */
 int ri_mlp_guess(ri_mlp* net, const ri_system* sys, double* t1, double* t2, void* stream);
 /* Binary file with sizes, scaling and parameters. */
 int ri_mlp_save(const ri_mlp* net, const char* path);

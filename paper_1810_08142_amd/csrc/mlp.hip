@@ -254,10 +254,11 @@ __global__ void features_kernel(const double* __restrict__ gov, const double* __
   }
 }
 
-// t2[row0 + r] += scale * y[r]
-__global__ void add_correction(double* t2, long row0, long n, const float* __restrict__ y, float scale) {
+// t2 = t2_MP2 * (1 + scale * y), rows row0 .. row0 + n
+__global__ void add_correction(double* t2, const double* __restrict__ t2m, long row0, long n,
+                               const float* __restrict__ y, float scale) {
   const long r = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r < n) t2[row0 + r] += static_cast<double>(scale) * static_cast<double>(y[r]);
+  if (r < n) t2[row0 + r] = t2m[row0 + r] * (1.0 + static_cast<double>(scale) * static_cast<double>(y[r]));
 }
 
 inline unsigned nblk(long n) { return static_cast<unsigned>((n + 255) / 256); }
@@ -673,15 +674,13 @@ int ri_mlp_guess(ri_mlp* net, const ri_system* sys, double* t1, double* t2, void
     nm.inv_std[k] = 1.f / net->stdv[k];
   }
   int rc = cc::mp2_with_integrals(sys, gov, t1, t2m, s);
-  if (rc == RI_OK) rc = check_hip(hipMemcpyAsync(t2, t2m, static_cast<size_t>(n) * sizeof(double),
-                                                 hipMemcpyDeviceToDevice, s), "ri_mlp_guess copy");
   if (rc == RI_OK) rc = mlp::reserve(net, chunk, s);
   for (long r0 = 0; r0 < n && rc == RI_OK; r0 += chunk) {
     const long nn = std::min(chunk, n - r0);
     mlp::features_kernel<<<mlp::nblk(nn), 256, 0, s>>>(gov, sys->eps, t2m, o, v, r0, nn, nm, X);
     if ((rc = check_launch("features_kernel"))) break;
     if ((rc = mlp::forward(net, X, nn, y, s))) break;
-    mlp::add_correction<<<mlp::nblk(nn), 256, 0, s>>>(t2, r0, nn, y, net->y_scale);
+    mlp::add_correction<<<mlp::nblk(nn), 256, 0, s>>>(t2, t2m, r0, nn, y, net->y_scale);
     rc = check_launch("add_correction");
   }
   if (rc == RI_OK) rc = cc::symmetrize_pairs(t2, o, v, s);

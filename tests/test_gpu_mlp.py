@@ -79,12 +79,12 @@ def test_zero_network_gives_mp2_and_correction_is_applied():
     assert np.abs(host(t1)).max() == 0.0
     assert np.abs(host(t2) - t2r).max() <= 1e-15 * np.abs(t2r).max()
     theta = np.zeros(net.num_params, dtype=np.float32)
-    theta[-1] = 0.5  # output bias only: every amplitude moves by y_scale * 0.5
+    theta[-1] = 0.5  # output bias only: every amplitude is scaled by 1 + y_scale * 0.5
     net.set_params(theta)
     net.set_scaling(np.zeros(8), np.ones(8), 0.01)
     _, t2c = net.guess(B, eps, o)
-    shift = 0.5 * float(np.float32(0.01))  # the scale is stored in FP32
-    assert float(np.abs(host(t2c) - (t2r + shift)).max()) <= 1e-12
+    factor = 1.0 + 0.5 * float(np.float32(0.01))  # the scale is stored in FP32
+    assert float(np.abs(host(t2c) - factor * t2r).max()) <= 1e-15 * np.abs(t2r).max()
 
 
 def test_save_load_roundtrip():
@@ -114,3 +114,25 @@ def test_training_reduces_loss():
         last = net.train_step(Xd, Yd, 3e-3, want_loss=False)
     last = net.train_step(Xd, Yd, 3e-3)
     assert last < 0.1 * first
+
+
+def test_trained_guess_cuts_iterations_on_held_out_system():
+    """Train on 128 small synthetic systems with the GPU kernels, then solve the
+    held-out o=24 v=384 Naux=1152 system from the MP2 and from the learned guess:
+    the learned start must reach the same solution in fewer iterations."""
+    from paper_1810_08142_amd import guess
+    from paper_1810_08142_amd.synthetic import training_shapes
+    print("building training set", flush=True)
+    X, Y, info = guess.build_dataset(training_shapes()[:128], 8192, seed=12345)
+    print("training on", X.shape[0], "samples", flush=True)
+    net, hist = guess.train(X, Y, epochs=20)
+    print("held-out loss", hist[0], hist[-1], flush=True)
+    assert hist[-1] < 0.5 * hist[0]
+    res = guess.evaluate(net, "c5")
+    print(res, flush=True)
+    ie = res["initial_error"]
+    assert ie["learned_rms"] < 0.5 * ie["mp2_rms"] and ie["learned_max"] < 0.5 * ie["mp2_max"]
+    assert res["mp2_guess"]["converged"] and res["learned_guess"]["converged"]
+    # the same CCSD solution (several exist), reached in fewer iterations
+    assert abs(res["delta_e_corr"]) <= 1e-8 and res["max_abs_delta_t2"] <= 1e-6
+    assert res["learned_guess"]["iterations"] < res["mp2_guess"]["iterations"]
