@@ -53,6 +53,20 @@ def traffic_from_profiles(kernel: str, workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def mfma_from_profiles(kernel: str, workload: str):
+    """Counter-measured MFMA utilisation of the kernel from a committed summary, if it
+    was taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_mfma.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if not d or d.get("source_hash") != source_hash():
+        return None
+    keep = ("mfma_util", "mfma_busy_frac", "executed_tflops", "algorithmic_share", "peak_tflops")
+    return {k: (round(d[k], 4) if isinstance(d.get(k), float) else d.get(k)) for k in keep}
+
+
 def make_inputs(workload: str):
     """B_vv, tau (host FP64) for a ladder workload; tau = MP2 t2 + t1 (x) t1."""
     import torch
@@ -164,7 +178,8 @@ def main():
     traffic = traffic_from_profiles(dom, args.workload)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": dom,
-                "kernel_ms_per_launch": round(kd["ms"] / kd["count"], 4)}
+                "kernel_ms_per_launch": round(kd["ms"] / kd["count"], 4),
+                "mfma_counters": mfma_from_profiles(dom, args.workload)}
 
     cpu = None
     if not args.no_cpu_baseline:
