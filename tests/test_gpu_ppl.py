@@ -148,3 +148,48 @@ def test_c2_full_size_sampled():
     assert np.abs(got - ref).max() / scale <= TOL
     assert np.array_equal(R, R.transpose(1, 0, 3, 2))
     assert np.isfinite(R).all()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_c4_full_size_sampled_fp64_and_mixed():
+    """c4 (o=48, v=768, naux=2304: B_vv, tau and R 10.9 GB each) through both ladder
+    precisions in one pass of the inputs; tau is the oracle's MP2 t2 + t1 (x) t1.
+    The oracle recomputes 64 sampled (a, b) pairs for all (i, j): FP64 to 1e-11,
+    split-bf16 within eps * L(|B|, |tau|) (eps = 2e-4, the split error model)."""
+    import torch
+    c = CONFIGS["c4"]
+    o, v, naux = c["o"], c["v"], c["naux"]
+    print("c4: drawing system", flush=True)
+    s = draw_system(o, v, naux, seed=c["seed"])
+    print("c4: oracle MP2 amplitudes", flush=True)
+    _, t2, _ = oc.mp2(s.B, s.eps, o)
+    tau = oc.make_tau(s.t1, t2)
+    del t2
+    B_vv = s.B_vv
+    del s
+    rng = np.random.default_rng(44)
+    pairs = [(int(a), int(b)) for a, b in rng.integers(0, v, size=(60, 2))] + [(0, 0), (v - 1, v - 1), (0, v - 1), (v - 1, 0)]
+    a_idx = torch.tensor([p[0] for p in pairs], device="cuda")
+    b_idx = torch.tensor([p[1] for p in pairs], device="cuda")
+    Bd, Td = dev(B_vv), dev(tau)
+    got = {}
+    for prec in ("fp64", "bf16x3"):
+        print(f"c4: GPU ladder {prec}", flush=True)
+        R = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+        _ppl().ppl(Bd, Td, R, precision=prec)
+        got[prec] = R[:, :, a_idx, b_idx].permute(2, 0, 1).cpu().numpy()
+        mirror = R[:, :, b_idx, a_idx].permute(2, 1, 0).cpu().numpy()
+        assert np.array_equal(got[prec], mirror)  # R^{ab}_{ij} = R^{ba}_{ji}, bitwise
+        assert np.isfinite(got[prec]).all()
+        del R
+    del Bd, Td
+    print("c4: oracle sample", flush=True)
+    ref = native.ppl_pairs(B_vv, tau, pairs)
+    assert np.abs(got["fp64"] - ref).max() / np.abs(ref).max() <= TOL
+    assert np.linalg.norm(got["fp64"] - ref) / np.linalg.norm(ref) <= TOL
+    print("c4: oracle bound sample", flush=True)
+    bound = 2e-4 * native.ppl_pairs(np.abs(B_vv), np.abs(tau), pairs)
+    err = np.abs(got["bf16x3"] - ref)
+    print("c4 bf16x3 max rel err", float(err.max() / np.abs(ref).max()), flush=True)
+    assert bool(np.all(err <= bound))
