@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "PPL TFLOP/s + MFMA util; time-to-converged E_corr (≤1 µEh), mixed vs FP64"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 accumulate)"}
-DOMINANT = {"fp64": "build_w_f64", "bf16x3": "build_w_bf16x3"}
+DOMINANT = {"fp64": "build_w_f64", "fp32": "build_w_f32", "bf16x3": "build_w_bf16x3"}
 
 
 def log(*a):
@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c2", "c4"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "bf16x3"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

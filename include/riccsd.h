@@ -38,7 +38,7 @@ extern "C" {
 
 /* ladder arithmetic */
 #define RI_PREC_FP64 0     /* FP64 MFMA throughout */
-#define RI_PREC_FP32 1     /* FP32 MFMA, FP32 accumulation */
+#define RI_PREC_FP32 1     /* operands rounded to FP32, FP32 MFMA, FP32 accumulation */
 #define RI_PREC_BF16X3 2   /* bf16 hi+lo split, three products, FP32 accumulation */
 
 const char* ri_status_str(int status);
@@ -73,7 +73,12 @@ int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double
 /* As ri_ppl with a choice of arithmetic (RI_PREC_*) and an optional caller
  * workspace: ws == NULL allocates internally; otherwise ws must be 256-byte
  * aligned and ws_bytes >= ri_ppl_workspace_bytes(o, v, naux, precision)
- * (RI_E_NOMEM if smaller).  The workspace contents are scratch. */
+ * (RI_E_NOMEM if smaller).  The workspace contents are scratch.  The reduced
+ * precisions round B_vv and the packed tau once to their operand type (FP32, or a
+ * bf16 hi + lo pair), rebuild the integrals with FP32 accumulation, round them
+ * again for the contraction and add the FP32 result into the FP64 R; the error of
+ * an element is bounded by 2e-4 times the ladder of |B_vv| and |tau| (and is
+ * typically 1e-6 of max |R| for bf16 hi + lo, less for FP32). */
 int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
               int precision, void* ws, size_t ws_bytes, void* stream);
 

@@ -38,37 +38,67 @@
 namespace ri {
 namespace ppl {
 
-constexpr int KC = 16;  // auxiliary functions staged per LDS step (FP64 path)
+constexpr int KC = 16;  // auxiliary functions (build) or cd slots (contraction) per LDS step
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef double double2_t __attribute__((ext_vector_type(2)));  // register-promotable (unlike double2)
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// D += A B on a 16x16x4 FP64 tile: lane l supplies A[l%16][l/16] and B[l/16][l%16]
-// and holds D[4r + l/16][l%16] in element r.
-__device__ inline double4_t mfma_f64(double a, double b, double4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// The FP64 and FP32 paths share their kernels; the element type picks the MFMA.
+// Both are 16x16x4 tiles with the same operand layout (lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]) but different result layouts: element r of lane l holds
+// D[drow(r, l)][l%16].
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double4_t acc_t;
+  typedef double2_t vec_t;  // one 16-byte load
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int drow(int r, int lane) { return 4 * r + (lane >> 4); }
+  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+};
+template <>
+struct Mfma<float> {
+  typedef f32x4_t acc_t;
+  typedef f32x4_t vec_t;
+  __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int drow(int r, int lane) { return 4 * (lane >> 4) + r; }
+  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+};
 
 // ---------------------------------------------------------------- 1. relayout
 // B[q][a][c] lives at B + q*qs + a*rs + c.  grid (naux_p, vp/16, vp/16), block 256
-__global__ __launch_bounds__(256) void relayout_b_f64(const double* __restrict__ B, long qs, long rs, int v,
-                                                      int naux, int vp, int naux_p, double* __restrict__ Bc) {
+template <class T>
+__device__ __forceinline__ void relayout_body(const double* __restrict__ B, long qs, long rs, int v, int naux, int vp,
+                                              int naux_p, T* __restrict__ Bc) {
   __shared__ double tile[TB][TB + 1];
   const int q = blockIdx.x, a0 = blockIdx.y * TB, c0 = blockIdx.z * TB;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int a = a0 + ty, c = c0 + tx;
   tile[ty][tx] = (a < v && c < v && q < naux) ? B[q * qs + a * rs + c] : 0.0;
   __syncthreads();
-  Bc[(static_cast<size_t>(c0 + ty) * naux_p + q) * vp + a0 + tx] = tile[tx][ty];
+  Bc[(static_cast<size_t>(c0 + ty) * naux_p + q) * vp + a0 + tx] = static_cast<T>(tile[tx][ty]);
+}
+__global__ __launch_bounds__(256) void relayout_b_f64(const double* __restrict__ B, long qs, long rs, int v,
+                                                      int naux, int vp, int naux_p, double* __restrict__ Bc) {
+  relayout_body<double>(B, qs, rs, v, naux, vp, naux_p, Bc);
+}
+__global__ __launch_bounds__(256) void relayout_b_f32(const double* __restrict__ B, long qs, long rs, int v,
+                                                      int naux, int vp, int naux_p, float* __restrict__ Bc) {
+  relayout_body<float>(B, qs, rs, v, naux, vp, naux_p, Bc);
 }
 
 // ---------------------------------------------------------------- 2. pack
 // out[slot][col], slot = pcd*256 + c_in*16 + d_in, col = packed (i,j).
 // sign > 0: i<=j columns, value of tau+ (with the 1/2 on c == d);
 // sign < 0: i<j columns, value of tau-.  Both taken from the pair-symmetric part
-// of tau.  grid (nbp, ncol/16), block 256
-__global__ __launch_bounds__(256) void pack_tau_f64(const double* __restrict__ tau, int o, int v,
-                                                    int ncol, int sign, double* __restrict__ out) {
+// of tau, formed in FP64 and rounded once to T.  grid (nbp, ncol/16), block 256
+template <class T>
+__device__ __forceinline__ void pack_body(const double* __restrict__ tau, int o, int v, int ncol, int sign,
+                                          T* __restrict__ out) {
   __shared__ double sv[256][NG + 1];
   int Cb, Db;
   tri_decode(blockIdx.x, Cb, Db);
@@ -100,20 +130,33 @@ __global__ __launch_bounds__(256) void pack_tau_f64(const double* __restrict__ t
   __syncthreads();
   for (int r = 0; r < 16; ++r) {
     const int slot = r * 16 + (t >> 4), cc = t & 15;
-    out[(static_cast<size_t>(blockIdx.x) * 256 + slot) * ncol + blockIdx.y * NG + cc] = sv[slot][cc];
+    out[(static_cast<size_t>(blockIdx.x) * 256 + slot) * ncol + blockIdx.y * NG + cc] = static_cast<T>(sv[slot][cc]);
   }
+}
+__global__ __launch_bounds__(256) void pack_tau_f64(const double* __restrict__ tau, int o, int v, int ncol, int sign,
+                                                    double* __restrict__ out) {
+  pack_body<double>(tau, o, v, ncol, sign, out);
+}
+__global__ __launch_bounds__(256) void pack_tau_f32(const double* __restrict__ tau, int o, int v, int ncol, int sign,
+                                                    float* __restrict__ out) {
+  pack_body<float>(tau, o, v, ncol, sign, out);
 }
 
 // ---------------------------------------------------------------- 3a. build
 // One workgroup: ab block pair (Ab, Bb) x one quarter (8 c by 8 d) of cd block pair
 // (Cb, Db).  Eight waves; wave w owns c in {2*(w>>1), +1} and d in {4*(w&1) .. +3}
 // of the quarter and accumulates (ac|bd) and (ad|bc) as 16x16 (a, b) MFMA tiles.
-// LDS holds, per 16-wide Q chunk, Bc for the 16 c/d rows x (16 a + 16 b) columns.
+// LDS holds, per KC-wide Q chunk, Bc for the 16 c/d rows x (16 a + 16 b) columns.
 // grid (nbp*4, slab_pairs), block 512
-__global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc, int naux_p, int vp,
-                                                   long slab0, long slab_M, int want_minus,
-                                                   double* __restrict__ Wp, double* __restrict__ Wm) {
-  __shared__ double lds[2][16][KC][32];  // [buf][x: 8 c then 8 d][k][e: 16 a then 16 b]
+template <class T>
+__device__ __forceinline__ void build_body(const T* __restrict__ Bc, int naux_p, int vp, long slab0, long slab_M,
+                                           int want_minus, T* __restrict__ Wp, T* __restrict__ Wm) {
+  typedef Mfma<T> MF;
+  typedef typename MF::vec_t vec_t;
+  constexpr int VEC = 16 / sizeof(T);          // elements per 16-byte load
+  constexpr int EV = 32 / VEC;                 // loads per (x, k) row of 32 e
+  constexpr int NV = 16 * KC * 32 / (512 * VEC);  // loads per thread per chunk
+  __shared__ T lds[2][16][KC][32];  // [buf][x: 8 c then 8 d][k][e: 16 a then 16 b]
   const int quarter = blockIdx.x & 3;
   const long pcd = blockIdx.x >> 2;
   const long pab_loc = blockIdx.y;
@@ -124,40 +167,40 @@ __global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc
   const int d_base = Db * TB + (quarter & 1) * 8;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 
-  // global -> register -> LDS staging: 8 double2 per thread per chunk.  Offsets are
-  // computed once; the chunk loop only adds the Q stride.
-  size_t goff[8];
-  int loff[8];
+  // global -> register -> LDS staging: NV 16-byte loads per thread per chunk.
+  // Offsets are computed once; the chunk loop only adds the Q stride.
+  size_t goff[NV];
+  int loff[NV];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int p2 = t + 512 * r;  // [0, 4096)
-    const int x = p2 >> 8, k = (p2 >> 4) & 15, e = (p2 & 15) * 2;
+  for (int r = 0; r < NV; ++r) {
+    const int p2 = t + 512 * r;
+    const int x = p2 / (KC * EV), k = (p2 / EV) % KC, e = (p2 % EV) * VEC;
     const int cg = x < 8 ? c_base + x : d_base + (x - 8);
     const int ag = e < 16 ? Ab * TB + e : Bb * TB + (e - 16);
     goff[r] = (static_cast<size_t>(cg) * naux_p + k) * vp + ag;
     loff[r] = (x * KC + k) * 32 + e;
   }
   const size_t qstride = static_cast<size_t>(vp) * KC;  // advance one chunk of Q
-  double* lds0 = &lds[0][0][0][0];
+  T* lds0 = &lds[0][0][0][0];
   constexpr int LBUF = 16 * KC * 32;
 
-  double4_t acc1[2][4], acc2[2][4];
+  typename MF::acc_t acc1[2][4], acc2[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      acc1[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
-      acc2[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+      acc1[i][j] = MF::zero();
+      acc2[i][j] = MF::zero();
     }
 
   const int xc0 = (w >> 1) * 2, xd0 = 8 + (w & 1) * 4;
   const int m = lane & 15, kq = lane >> 4;
   const int nchunks = naux_p / KC;
-  double2_t stage[8];
+  vec_t stage[NV];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const double2_t*>(Bc + goff[r]);
+  for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r]);
 #pragma unroll
-  for (int r = 0; r < 8; ++r) *reinterpret_cast<double2_t*>(lds0 + loff[r]) = stage[r];
+  for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(lds0 + loff[r]) = stage[r];
   __syncthreads();
   for (int ch = 0; ch < nchunks; ++ch) {
     const int buf = ch & 1;
@@ -165,12 +208,12 @@ __global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc
     if (more) {
       const size_t qo = static_cast<size_t>(ch + 1) * qstride;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const double2_t*>(Bc + goff[r] + qo);
+      for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r] + qo);
     }
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int kk = 4 * s + kq;
-      double a_c[2], b_c[2], a_d[4], b_d[4];
+      T a_c[2], b_c[2], a_d[4], b_d[4];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         a_c[i] = lds[buf][xc0 + i][kk][m];
@@ -185,20 +228,20 @@ __global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          acc1[i][j] = mfma_f64(a_c[i], b_d[j], acc1[i][j]);  // (ac|bd)
-          acc2[i][j] = mfma_f64(a_d[j], b_c[i], acc2[i][j]);  // (ad|bc)
+          acc1[i][j] = MF::mma(a_c[i], b_d[j], acc1[i][j]);  // (ac|bd)
+          acc2[i][j] = MF::mma(a_d[j], b_c[i], acc2[i][j]);  // (ad|bc)
         }
     }
     if (more) {
-      double* dst = lds0 + (buf ^ 1) * LBUF;
+      T* dst = lds0 + (buf ^ 1) * LBUF;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) *reinterpret_cast<double2_t*>(dst + loff[r]) = stage[r];
+      for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(dst + loff[r]) = stage[r];
     }
     __syncthreads();
   }
 
-  // epilogue: W+-[slot][ab slot].  The f64 16x16x4 MFMA leaves D[4r + lane/16][lane%16]
-  // in register r of each lane: row a_in = 4r + (lane>>4), column b_in = lane&15.
+  // epilogue: W+-[slot][ab slot]; element r of a lane is row a_in = drow(r, lane),
+  // column b_in = lane & 15 of the (a, b) tile.
   const size_t col0 = static_cast<size_t>(pab_loc) * 256;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -209,36 +252,51 @@ __global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc
       const size_t row = (static_cast<size_t>(pcd) * 256 + c_in * 16 + d_in) * slab_M + col0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a_in = 4 * r + (lane >> 4), b_in = lane & 15;
-        const double v1 = acc1[i][j][r], v2 = acc2[i][j][r];
+        const int a_in = MF::drow(r, lane), b_in = lane & 15;
+        const T v1 = acc1[i][j][r], v2 = acc2[i][j][r];
         Wp[row + a_in * 16 + b_in] = v1 + v2;
         if (want_minus) Wm[row + a_in * 16 + b_in] = v1 - v2;
       }
     }
 }
+__global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc, int naux_p, int vp, long slab0,
+                                                   long slab_M, int want_minus, double* __restrict__ Wp,
+                                                   double* __restrict__ Wm) {
+  build_body<double>(Bc, naux_p, vp, slab0, slab_M, want_minus, Wp, Wm);
+}
+__global__ __launch_bounds__(512) void build_w_f32(const float* __restrict__ Bc, int naux_p, int vp, long slab0,
+                                                   long slab_M, int want_minus, float* __restrict__ Wp,
+                                                   float* __restrict__ Wm) {
+  build_body<float>(Bc, naux_p, vp, slab0, slab_M, want_minus, Wp, Wm);
+}
 
 // ---------------------------------------------------------------- 3b. contract
 // C[m][n] = sum_k W[k][m] T[k][n];  tile 64 (m) x 16*NTW (n); 4 waves, wave w owns
 // rows 16w..16w+15 and all columns.  grid (ncol/(16*NTW), M/64), block 256
-template <int NTW>
-__global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W, const double* __restrict__ T,
-                                                    long K, long M, int ncol, double* __restrict__ C) {
+template <class T, int NTW>
+__device__ __forceinline__ void contract_body(const T* __restrict__ W, const T* __restrict__ Tt, long K, long M,
+                                              int ncol, T* __restrict__ C) {
   // W rows have stride M (the slab width); C has NTW*16*gridDim.x columns
+  typedef Mfma<T> MF;
+  typedef typename MF::vec_t vec_t;
   constexpr int BN = 16 * NTW;
-  __shared__ double sA[2][KC][64];
-  __shared__ double sB[2][KC][BN];
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int AV = 64 / VEC;                  // loads per k row of the A tile
+  constexpr int NA = KC * 64 / (256 * VEC);     // A loads per thread per chunk
+  __shared__ T sA[2][KC][64];
+  __shared__ T sB[2][KC][BN];
   unsigned tx, ty;
   xcd_tile(tx, ty);
   const long n0 = static_cast<long>(tx) * BN, m0 = static_cast<long>(ty) * 64;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 
   // staging offsets (computed once; the chunk loop adds k0 * row stride)
-  long aoff[2], boff[NTW];
-  int alo[2], blo[NTW];
+  long aoff[NA], boff[NTW];
+  int alo[NA], blo[NTW];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < NA; ++r) {
     const int p2 = t + 256 * r;
-    const int k = p2 >> 5, mm = (p2 & 31) * 2;
+    const int k = p2 / AV, mm = (p2 % AV) * VEC;
     aoff[r] = k * M + m0 + mm;
     alo[r] = k * 64 + mm;
   }
@@ -249,22 +307,22 @@ __global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W
     boff[r] = static_cast<long>(k) * ncol + n0 + nn;
     blo[r] = k * BN + nn;
   }
-  double2_t ra[2];
-  double rb[NTW];
-  double* sA0 = &sA[0][0][0];
-  double* sB0 = &sB[0][0][0];
+  vec_t ra[NA];
+  T rb[NTW];
+  T* sA0 = &sA[0][0][0];
+  T* sB0 = &sB[0][0][0];
 
-  double4_t acc[NTW];
+  typename MF::acc_t acc[NTW];
 #pragma unroll
-  for (int u = 0; u < NTW; ++u) acc[u] = double4_t{0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < NTW; ++u) acc[u] = MF::zero();
   const int m = lane & 15, kq = lane >> 4;
   const long nchunks = K / KC;
 #pragma unroll
-  for (int r = 0; r < 2; ++r) ra[r] = *reinterpret_cast<const double2_t*>(W + aoff[r]);
+  for (int r = 0; r < NA; ++r) ra[r] = *reinterpret_cast<const vec_t*>(W + aoff[r]);
 #pragma unroll
-  for (int r = 0; r < NTW; ++r) rb[r] = T[boff[r]];
+  for (int r = 0; r < NTW; ++r) rb[r] = Tt[boff[r]];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) *reinterpret_cast<double2_t*>(sA0 + alo[r]) = ra[r];
+  for (int r = 0; r < NA; ++r) *reinterpret_cast<vec_t*>(sA0 + alo[r]) = ra[r];
 #pragma unroll
   for (int r = 0; r < NTW; ++r) sB0[blo[r]] = rb[r];
   __syncthreads();
@@ -274,20 +332,20 @@ __global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W
     if (more) {
       const long k0 = (ch + 1) * KC;
 #pragma unroll
-      for (int r = 0; r < 2; ++r) ra[r] = *reinterpret_cast<const double2_t*>(W + aoff[r] + k0 * M);
+      for (int r = 0; r < NA; ++r) ra[r] = *reinterpret_cast<const vec_t*>(W + aoff[r] + k0 * M);
 #pragma unroll
-      for (int r = 0; r < NTW; ++r) rb[r] = T[boff[r] + k0 * ncol];
+      for (int r = 0; r < NTW; ++r) rb[r] = Tt[boff[r] + k0 * ncol];
     }
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int kk = 4 * s + kq;
-      const double a = sA[buf][kk][w * 16 + m];
+      const T a = sA[buf][kk][w * 16 + m];
 #pragma unroll
-      for (int u = 0; u < NTW; ++u) acc[u] = mfma_f64(a, sB[buf][kk][u * 16 + m], acc[u]);
+      for (int u = 0; u < NTW; ++u) acc[u] = MF::mma(a, sB[buf][kk][u * 16 + m], acc[u]);
     }
     if (more) {
 #pragma unroll
-      for (int r = 0; r < 2; ++r) *reinterpret_cast<double2_t*>(sA0 + (buf ^ 1) * KC * 64 + alo[r]) = ra[r];
+      for (int r = 0; r < NA; ++r) *reinterpret_cast<vec_t*>(sA0 + (buf ^ 1) * KC * 64 + alo[r]) = ra[r];
 #pragma unroll
       for (int r = 0; r < NTW; ++r) sB0[(buf ^ 1) * KC * BN + blo[r]] = rb[r];
     }
@@ -297,9 +355,19 @@ __global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W
   for (int u = 0; u < NTW; ++u)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const long row = m0 + w * 16 + 4 * r + kq;  // D[4r + lane/16][lane%16]
+      const long row = m0 + w * 16 + MF::drow(r, lane);
       C[row * ncol + n0 + u * 16 + m] = acc[u][r];
     }
+}
+template <int NTW>
+__global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W, const double* __restrict__ Tt,
+                                                    long K, long M, int ncol, double* __restrict__ C) {
+  contract_body<double, NTW>(W, Tt, K, M, ncol, C);
+}
+template <int NTW>
+__global__ __launch_bounds__(256) void contract_f32(const float* __restrict__ W, const float* __restrict__ Tt,
+                                                    long K, long M, int ncol, float* __restrict__ C) {
+  contract_body<float, NTW>(W, Tt, K, M, ncol, C);
 }
 
 // ---------------------------------------------------------------- 3c. unpack
@@ -383,16 +451,18 @@ struct Plan {
   long nbp, K;
   int po, pm, NP, NM, ntw_p, ntw_m;
   long slab_bp, slab_M;
+  size_t esize;  // bytes per element of the staged operands (8 FP64, 4 FP32)
   size_t n_Bc, n_Tp, n_Tm, n_W, n_S, n_A;
   size_t bytes;
 };
 
-static bool make_plan(int o, int v, int naux, Plan& p) {
+static bool make_plan(int o, int v, int naux, size_t esize, Plan& p) {
   if (o <= 0 || v <= 0 || naux <= 0) return false;
   if (o > 4096 || v > 65536 || naux > (1 << 24)) return false;
   p.o = o;
   p.v = v;
   p.naux = naux;
+  p.esize = esize;
   p.nb = (v + TB - 1) / TB;
   p.vp = p.nb * TB;
   p.naux_p = static_cast<int>(round_up(naux, KC));
@@ -405,7 +475,7 @@ static bool make_plan(int o, int v, int naux, Plan& p) {
   if (p.pm == 0) p.NM = 0;
   const int nw = p.pm > 0 ? 2 : 1;
   const long budget = env_long("RI_PPL_W_BYTES", 16L << 30);
-  long bp = budget / (static_cast<long>(nw) * p.K * 256 * 8);
+  long bp = budget / (static_cast<long>(nw) * p.K * 256 * static_cast<long>(esize));
   bp = bp < 1 ? 1 : bp;
   bp = bp > p.nbp ? p.nbp : bp;
   bp = bp > 65535 ? 65535 : bp;
@@ -420,60 +490,104 @@ static bool make_plan(int o, int v, int naux, Plan& p) {
   p.n_A = static_cast<size_t>(p.slab_M) * p.NM;
   size_t b = 0;
   for (size_t n : {p.n_Bc, p.n_Tp, p.n_Tm, p.n_W, p.pm > 0 ? p.n_W : 0, p.n_S, p.n_A})
-    b = round_up(b, 256) + n * sizeof(double);
+    b = round_up(b, 256) + n * esize;
   p.bytes = round_up(b, 256);
   return true;
 }
 
-// rows: number of C rows (multiple of 64) computed; ldw: row stride of W
-template <int NTW>
-static void launch_contract_t(const double* W, const double* T, long K, long ldw, long rows, int ncol,
-                              double* C, hipStream_t s) {
-  dim3 grid(ncol / (16 * NTW), rows / 64);
-  contract_f64<NTW><<<grid, 256, 0, s>>>(W, T, K, ldw, ncol, C);
-}
+// Kernel choice by element type (names stay distinct in profiles).
+struct K64 {
+  typedef double T;
+  static constexpr const char* relayout = "relayout_b_f64";
+  static constexpr const char* pack = "pack_tau_f64";
+  static constexpr const char* build = "build_w_f64";
+  static constexpr const char* contract = "contract_f64";
+  static constexpr const char* unpack = "unpack_f64";
+  static void relayout_k(dim3 g, hipStream_t s, const double* B, long qs, long rs, int v, int naux, int vp, int np,
+                         T* Bc) {
+    relayout_b_f64<<<g, 256, 0, s>>>(B, qs, rs, v, naux, vp, np, Bc);
+  }
+  static void pack_k(dim3 g, hipStream_t s, const double* tau, int o, int v, int ncol, int sign, T* out) {
+    pack_tau_f64<<<g, 256, 0, s>>>(tau, o, v, ncol, sign, out);
+  }
+  static void build_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, T* Wp, T* Wm) {
+    build_w_f64<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, Wp, Wm);
+  }
+  template <int NTW>
+  static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C) {
+    contract_f64<NTW><<<g, 256, 0, s>>>(W, Tt, K, M, ncol, C);
+  }
+};
+struct K32 {
+  typedef float T;
+  static constexpr const char* relayout = "relayout_b_f32";
+  static constexpr const char* pack = "pack_tau_f32";
+  static constexpr const char* build = "build_w_f32";
+  static constexpr const char* contract = "contract_f32";
+  static constexpr const char* unpack = "unpack_f32";
+  static void relayout_k(dim3 g, hipStream_t s, const double* B, long qs, long rs, int v, int naux, int vp, int np,
+                         T* Bc) {
+    relayout_b_f32<<<g, 256, 0, s>>>(B, qs, rs, v, naux, vp, np, Bc);
+  }
+  static void pack_k(dim3 g, hipStream_t s, const double* tau, int o, int v, int ncol, int sign, T* out) {
+    pack_tau_f32<<<g, 256, 0, s>>>(tau, o, v, ncol, sign, out);
+  }
+  static void build_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, T* Wp, T* Wm) {
+    build_w_f32<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, Wp, Wm);
+  }
+  template <int NTW>
+  static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C) {
+    contract_f32<NTW><<<g, 256, 0, s>>>(W, Tt, K, M, ncol, C);
+  }
+};
 
-static void launch_contract(int ntw, const double* W, const double* T, long K, long ldw, long rows,
-                            int ncol, double* C, hipStream_t s) {
+// rows: number of C rows (multiple of 64) computed; ldw: row stride of W
+template <class KS>
+static void launch_contract(int ntw, const typename KS::T* W, const typename KS::T* Tt, long K, long ldw, long rows,
+                            int ncol, typename KS::T* C, hipStream_t s) {
+  const unsigned gy = static_cast<unsigned>(rows / 64);
   switch (ntw) {
-    case 1: launch_contract_t<1>(W, T, K, ldw, rows, ncol, C, s); break;
-    case 2: launch_contract_t<2>(W, T, K, ldw, rows, ncol, C, s); break;
-    case 3: launch_contract_t<3>(W, T, K, ldw, rows, ncol, C, s); break;
-    case 4: launch_contract_t<4>(W, T, K, ldw, rows, ncol, C, s); break;
-    case 5: launch_contract_t<5>(W, T, K, ldw, rows, ncol, C, s); break;
-    case 6: launch_contract_t<6>(W, T, K, ldw, rows, ncol, C, s); break;
-    case 7: launch_contract_t<7>(W, T, K, ldw, rows, ncol, C, s); break;
-    case 8: launch_contract_t<8>(W, T, K, ldw, rows, ncol, C, s); break;
-    case 9: launch_contract_t<9>(W, T, K, ldw, rows, ncol, C, s); break;
-    default: launch_contract_t<10>(W, T, K, ldw, rows, ncol, C, s); break;
+    case 1: KS::template contract_k<1>(dim3(ncol / 16, gy), s, W, Tt, K, ldw, ncol, C); break;
+    case 2: KS::template contract_k<2>(dim3(ncol / 32, gy), s, W, Tt, K, ldw, ncol, C); break;
+    case 3: KS::template contract_k<3>(dim3(ncol / 48, gy), s, W, Tt, K, ldw, ncol, C); break;
+    case 4: KS::template contract_k<4>(dim3(ncol / 64, gy), s, W, Tt, K, ldw, ncol, C); break;
+    case 5: KS::template contract_k<5>(dim3(ncol / 80, gy), s, W, Tt, K, ldw, ncol, C); break;
+    case 6: KS::template contract_k<6>(dim3(ncol / 96, gy), s, W, Tt, K, ldw, ncol, C); break;
+    case 7: KS::template contract_k<7>(dim3(ncol / 112, gy), s, W, Tt, K, ldw, ncol, C); break;
+    case 8: KS::template contract_k<8>(dim3(ncol / 128, gy), s, W, Tt, K, ldw, ncol, C); break;
+    case 9: KS::template contract_k<9>(dim3(ncol / 144, gy), s, W, Tt, K, ldw, ncol, C); break;
+    default: KS::template contract_k<10>(dim3(ncol / 160, gy), s, W, Tt, K, ldw, ncol, C); break;
   }
 }
 
-static int run_f64(const Plan& p, const double* B_vv, long qs, long rs, const double* tau, double* R,
-                   void* ws, hipStream_t s) {
+template <class KS>
+static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const double* tau, double* R, void* ws,
+                    hipStream_t s) {
+  typedef typename KS::T T;
   Carve cv(ws, p.bytes);
-  double* Bc = cv.take<double>(p.n_Bc);
-  double* Tp = cv.take<double>(p.n_Tp);
-  double* Tm = cv.take<double>(p.n_Tm);
-  double* Wp = cv.take<double>(p.n_W);
-  double* Wm = cv.take<double>(p.pm > 0 ? p.n_W : 0);
-  double* S = cv.take<double>(p.n_S);
-  double* A = cv.take<double>(p.n_A);
+  T* Bc = cv.take<T>(p.n_Bc);
+  T* Tp = cv.take<T>(p.n_Tp);
+  T* Tm = cv.take<T>(p.n_Tm);
+  T* Wp = cv.take<T>(p.n_W);
+  T* Wm = cv.take<T>(p.pm > 0 ? p.n_W : 0);
+  T* S = cv.take<T>(p.n_S);
+  T* A = cv.take<T>(p.n_A);
 
+  const double es = static_cast<double>(sizeof(T));
   const double vv = static_cast<double>(p.v) * p.v, oo = static_cast<double>(p.o) * p.o;
   const double pv = p.v * (p.v + 1.0) / 2, pvm = p.v * (p.v - 1.0) / 2;
   {
-    ProfScope ps(s, "relayout_b_f64", 0.0, 8.0 * vv * p.naux * 2);
-    relayout_b_f64<<<dim3(p.naux_p, p.nb, p.nb), 256, 0, s>>>(B_vv, qs, rs, p.v, p.naux, p.vp, p.naux_p, Bc);
-    RI_TRY(check_launch("relayout_b_f64"));
+    ProfScope ps(s, KS::relayout, 0.0, (8.0 + es) * vv * p.naux);
+    KS::relayout_k(dim3(p.naux_p, p.nb, p.nb), s, B_vv, qs, rs, p.v, p.naux, p.vp, p.naux_p, Bc);
+    RI_TRY(check_launch(KS::relayout));
   }
   {
-    ProfScope ps(s, "pack_tau_f64", 0.0, 8.0 * (oo * vv + pv * p.po + pvm * p.pm));
-    pack_tau_f64<<<dim3(p.nbp, p.NP / NG), 256, 0, s>>>(tau, p.o, p.v, p.NP, +1, Tp);
-    RI_TRY(check_launch("pack_tau_f64(+)"));
+    ProfScope ps(s, KS::pack, 0.0, 8.0 * oo * vv + es * (pv * p.po + pvm * p.pm));
+    KS::pack_k(dim3(p.nbp, p.NP / NG), s, tau, p.o, p.v, p.NP, +1, Tp);
+    RI_TRY(check_launch(KS::pack));
     if (p.pm > 0) {
-      pack_tau_f64<<<dim3(p.nbp, p.NM / NG), 256, 0, s>>>(tau, p.o, p.v, p.NM, -1, Tm);
-      RI_TRY(check_launch("pack_tau_f64(-)"));
+      KS::pack_k(dim3(p.nbp, p.NM / NG), s, tau, p.o, p.v, p.NM, -1, Tm);
+      RI_TRY(check_launch(KS::pack));
     }
   }
   for (long slab0 = 0; slab0 < p.nbp; slab0 += p.slab_bp) {
@@ -483,48 +597,56 @@ static int run_f64(const Plan& p, const double* B_vv, long qs, long rs, const do
     count_pairs(p.v, slab0, npairs, le, lt);
     {
       // per valid (a <= b): the v x v matrix (ac|bd) over all c, d, naux products each
-      ProfScope ps(s, "build_w_f64", 2.0 * p.naux * vv * le);
-      build_w_f64<<<dim3(p.nbp * 4, npairs), 512, 0, s>>>(Bc, p.naux_p, p.vp, slab0, p.slab_M,
-                                                          p.pm > 0 ? 1 : 0, Wp, Wm);
-      RI_TRY(check_launch("build_w_f64"));
+      ProfScope ps(s, KS::build, 2.0 * p.naux * vv * le);
+      KS::build_k(dim3(p.nbp * 4, npairs), s, Bc, p.naux_p, p.vp, slab0, p.slab_M, p.pm > 0 ? 1 : 0, Wp, Wm);
+      RI_TRY(check_launch(KS::build));
     }
     {
-      ProfScope ps(s, "contract_f64", 2.0 * (le * pv * p.po + lt * pvm * p.pm));
-      launch_contract(p.ntw_p, Wp, Tp, p.K, p.slab_M, M, p.NP, S, s);
-      RI_TRY(check_launch("contract_f64(+)"));
+      ProfScope ps(s, KS::contract, 2.0 * (le * pv * p.po + lt * pvm * p.pm));
+      launch_contract<KS>(p.ntw_p, Wp, Tp, p.K, p.slab_M, M, p.NP, S, s);
+      RI_TRY(check_launch(KS::contract));
       if (p.pm > 0) {
-        launch_contract(p.ntw_m, Wm, Tm, p.K, p.slab_M, M, p.NM, A, s);
-        RI_TRY(check_launch("contract_f64(-)"));
+        launch_contract<KS>(p.ntw_m, Wm, Tm, p.K, p.slab_M, M, p.NM, A, s);
+        RI_TRY(check_launch(KS::contract));
       }
     }
     {
-      ProfScope ps(s, "unpack_f64", 0.0, 16.0 * oo * (le + lt));
-      unpack_kernel<double><<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R);
-      RI_TRY(check_launch("unpack_f64"));
+      ProfScope ps(s, KS::unpack, 0.0, 16.0 * oo * (le + lt));
+      unpack_kernel<T><<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R);
+      RI_TRY(check_launch(KS::unpack));
     }
   }
   return RI_OK;
 }
 
+// Runs the FP64 or FP32 path of plan p on workspace ws (allocated when null).
+static int run_typed(const Plan& p, int precision, const double* B_vv, long qs, long rs, const double* tau,
+                     double* R, void* ws, hipStream_t s) {
+  void* buf = ws;
+  if (!buf) RI_TRY(dev_alloc(&buf, p.bytes, s));
+  const int rc = precision == RI_PREC_FP32 ? run_plan<K32>(p, B_vv, qs, rs, tau, R, buf, s)
+                                           : run_plan<K64>(p, B_vv, qs, rs, tau, R, buf, s);
+  if (!ws) dev_free(buf, s);
+  return rc;
+}
+
+static size_t esize_of(int precision) { return precision == RI_PREC_FP32 ? 4 : 8; }
+
 }  // namespace ppl
 
 int ppl_strided(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
                 int precision, hipStream_t s) {
+  if (precision == RI_PREC_BF16X3) return ppl::bf16x3_run(B, qs, rs, tau, o, v, naux, R, nullptr, 0, s);
+  if (precision != RI_PREC_FP64 && precision != RI_PREC_FP32) {
+    set_error("ladder: unknown precision %d", precision);
+    return RI_E_ARG;
+  }
   ppl::Plan p;
-  if (!ppl::make_plan(o, v, naux, p)) {
+  if (!ppl::make_plan(o, v, naux, ppl::esize_of(precision), p)) {
     set_error("ladder: invalid sizes o=%d v=%d naux=%d", o, v, naux);
     return RI_E_ARG;
   }
-  if (precision == RI_PREC_BF16X3) return ppl::bf16x3_run(B, qs, rs, tau, o, v, naux, R, nullptr, 0, s);
-  if (precision != RI_PREC_FP64) {
-    set_error("ladder: precision %d not available in this build", precision);
-    return RI_E_UNSUPPORTED;
-  }
-  void* buf = nullptr;
-  RI_TRY(dev_alloc(&buf, p.bytes, s));
-  const int rc = ppl::run_f64(p, B, qs, rs, tau, R, buf, s);
-  dev_free(buf, s);
-  return rc;
+  return ppl::run_typed(p, precision, B, qs, rs, tau, R, nullptr, s);
 }
 
 }  // namespace ri
@@ -536,8 +658,8 @@ extern "C" {
 size_t ri_ppl_workspace_bytes(int o, int v, int naux, int precision) {
   ppl::Plan p;
   if (precision == RI_PREC_BF16X3) return ppl::bf16x3_workspace_bytes(o, v, naux);
-  if (precision != RI_PREC_FP64) return 0;
-  if (!ppl::make_plan(o, v, naux, p)) return 0;
+  if (precision != RI_PREC_FP64 && precision != RI_PREC_FP32) return 0;
+  if (!ppl::make_plan(o, v, naux, ppl::esize_of(precision), p)) return 0;
   return p.bytes;
 }
 
@@ -560,13 +682,9 @@ int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, dou
     return RI_E_ARG;
   }
   ppl::Plan p;
-  if (!ppl::make_plan(o, v, naux, p)) {
+  if (!ppl::make_plan(o, v, naux, ppl::esize_of(precision), p)) {
     set_error("ri_ppl: invalid sizes o=%d v=%d naux=%d", o, v, naux);
     return RI_E_ARG;
-  }
-  if (precision == RI_PREC_FP32) {
-    set_error("ri_ppl: precision %d not available in this build", precision);
-    return RI_E_UNSUPPORTED;
   }
   const size_t nB = static_cast<size_t>(naux) * v * v * sizeof(double);
   const size_t nT = static_cast<size_t>(o) * o * v * v * sizeof(double);
@@ -586,24 +704,11 @@ int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, dou
   }
   if (precision == RI_PREC_BF16X3)
     return ppl::bf16x3_run(B_vv, static_cast<long>(v) * v, v, tau, o, v, naux, R, ws, ws_bytes, s);
-  void* buf = ws;
-  bool own = false;
-  if (ws) {
-    if (ws_bytes < p.bytes) {
-      set_error("ri_ppl: workspace of %zu bytes is smaller than the %zu required", ws_bytes, p.bytes);
-      return RI_E_NOMEM;
-    }
-    if (reinterpret_cast<uintptr_t>(ws) & 255) {
-      set_error("ri_ppl: workspace must be 256-byte aligned");
-      return RI_E_ARG;
-    }
-  } else {
-    RI_TRY(dev_alloc(&buf, p.bytes, s));
-    own = true;
+  if (ws && ws_bytes < p.bytes) {
+    set_error("ri_ppl: workspace of %zu bytes is smaller than the %zu required", ws_bytes, p.bytes);
+    return RI_E_NOMEM;
   }
-  int rc = ppl::run_f64(p, B_vv, static_cast<long>(v) * v, v, tau, R, buf, s);
-  if (own) dev_free(buf, s);
-  return rc;
+  return ppl::run_typed(p, precision, B_vv, static_cast<long>(v) * v, v, tau, R, ws, s);
 }
 
 int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream) {

@@ -1,13 +1,14 @@
-"""Mixed-precision ladder (split-bf16, three products, FP32 accumulation) on the GPU.
+"""Reduced-precision ladders on the GPU: split-bf16 (three products) and plain FP32
+operands, both on MFMA with FP32 accumulation.
 
 Error model: a split operand x = hi + lo is exact to 2^-18 |x|, and dropping lo*lo
-adds another 2^-18 |a||b|, so one split product is within 3 * 2^-18 |a||b|.  The
-build and the contraction each split once and accumulate in FP32, hence, element
-by element,
+adds another 2^-18 |a||b|, so one split product is within 3 * 2^-18 |a||b|; an FP32
+operand is exact to 2^-24 |x|.  The build and the contraction each round their
+operands once and accumulate in FP32, hence, element by element,
 
     |R_mixed - R_fp64| <= eps * sum_cd sum_Q |B_ac| |B_bd| |tau^{cd}_{ij}|  = eps * L(|B|, |tau|)
 
-with eps = 2e-4 (two split stages, FP32 accumulation over up to ~1e4 terms).  The
+with eps = 2e-4 (two rounding stages, FP32 accumulation over up to ~1e4 terms).  The
 right-hand side is the oracle's ladder of the element-wise absolute values."""
 import os
 
@@ -32,12 +33,16 @@ def _ladder(B_vv, tau, precision="bf16x3"):
     return host(R)
 
 
+PRECS = ["bf16x3", "fp32"]
+
+
+@pytest.mark.parametrize("precision", PRECS)
 @pytest.mark.parametrize("o,v,naux", [(1, 3, 2), (2, 17, 7), (3, 33, 20), (4, 24, 96), (5, 40, 37), (2, 50, 130)])
-def test_mixed_within_split_error_bound(o, v, naux):
-    print(f"bf16x3 o={o} v={v} naux={naux}", flush=True)
+def test_mixed_within_split_error_bound(o, v, naux, precision):
+    print(f"{precision} o={o} v={v} naux={naux}", flush=True)
     s = draw_system(o, v, naux, seed=900 + v)
     tau = draw_pair_symmetric(o, v, 901 + v)
-    got = _ladder(s.B_vv, tau)
+    got = _ladder(s.B_vv, tau, precision)
     ref = native.ppl(s.B_vv, tau)
     bound = EPS * native.ppl(np.abs(s.B_vv), np.abs(tau))
     err = np.abs(got - ref)
@@ -47,28 +52,41 @@ def test_mixed_within_split_error_bound(o, v, naux):
     assert float(err.max()) > 0.0
 
 
-def test_mixed_nonsymmetric_factors_and_symmetry():
+@pytest.mark.parametrize("precision", PRECS)
+def test_mixed_nonsymmetric_factors_and_symmetry(precision):
     o, v, naux = 3, 29, 17
     s = draw_system(o, v, naux, seed=911, scale=0.2)
     t1 = draw_matrix((o, v), 912, 0.1)
     Bd = np.ascontiguousarray(oc.dress(s.B, t1)[:, o:, o:])
     tau = draw_pair_symmetric(o, v, 913)
-    got = _ladder(Bd, tau)
+    got = _ladder(Bd, tau, precision)
     ref = native.ppl(Bd, tau)
     assert bool(np.all(np.abs(got - ref) <= EPS * native.ppl(np.abs(Bd), np.abs(tau))))
     # exact pair symmetry needs (ac|bd) - (ad|bc) to vanish exactly at a == b
     assert np.array_equal(got, got.transpose(1, 0, 3, 2))
-    assert np.array_equal(got, _ladder(Bd, tau))
+    assert np.array_equal(got, _ladder(Bd, tau, precision))
 
 
-def test_mixed_slabs_do_not_change_result():
+def test_fp32_operands_are_more_accurate_than_split_bf16():
+    o, v, naux = 4, 40, 60
+    s = draw_system(o, v, naux, seed=915)
+    tau = draw_pair_symmetric(o, v, 916)
+    ref = native.ppl(s.B_vv, tau)
+    e32 = np.abs(_ladder(s.B_vv, tau, "fp32") - ref).max()
+    e16 = np.abs(_ladder(s.B_vv, tau, "bf16x3") - ref).max()
+    print("max error fp32", e32, "bf16x3", e16, flush=True)
+    assert 0.0 < e32 < e16
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_mixed_slabs_do_not_change_result(precision):
     o, v, naux = 3, 70, 18
     s = draw_system(o, v, naux, seed=921)
     tau = draw_pair_symmetric(o, v, 922)
-    R1 = _ladder(s.B_vv, tau)
+    R1 = _ladder(s.B_vv, tau, precision)
     os.environ["RI_PPL_SLAB_PAIRS"] = "3"
     try:
-        R2 = _ladder(s.B_vv, tau)
+        R2 = _ladder(s.B_vv, tau, precision)
     finally:
         del os.environ["RI_PPL_SLAB_PAIRS"]
     assert np.array_equal(R1, R2)
@@ -80,25 +98,27 @@ def test_mixed_c2_full_size_sampled():
     s = draw_system(o, v, naux, seed=c["seed"])
     _, t2, _ = oc.mp2(s.B, s.eps, o)
     tau = oc.make_tau(s.t1, t2)
-    R = _ladder(s.B_vv, tau)
     rng = np.random.default_rng(8)
     pairs = [(int(a), int(b)) for a, b in rng.integers(0, v, size=(24, 2))] + [(0, 0), (v - 1, 0)]
     ref = native.ppl_pairs(s.B_vv, tau, pairs)
     bound = EPS * native.ppl_pairs(np.abs(s.B_vv), np.abs(tau), pairs)
-    got = np.stack([R[:, :, a, b] for a, b in pairs])
-    print("c2 bf16x3 max rel err", float(np.abs(got - ref).max() / np.abs(ref).max()), flush=True)
-    assert bool(np.all(np.abs(got - ref) <= bound))
-    assert np.array_equal(R, R.transpose(1, 0, 3, 2))
+    for precision in PRECS:
+        R = _ladder(s.B_vv, tau, precision)
+        got = np.stack([R[:, :, a, b] for a, b in pairs])
+        print(f"c2 {precision} max rel err", float(np.abs(got - ref).max() / np.abs(ref).max()), flush=True)
+        assert bool(np.all(np.abs(got - ref) <= bound))
+        assert np.array_equal(R, R.transpose(1, 0, 3, 2))
 
 
-def test_ccsd_with_mixed_ladder_energy_within_microhartree():
+@pytest.mark.parametrize("precision", PRECS)
+def test_ccsd_with_mixed_ladder_energy_within_microhartree(precision):
     from paper_1810_08142_amd import ccsd
     c = CONFIGS["c1"]
     o, v, naux = c["o"], c["v"], c["naux"]
     s = draw_system(o, v, naux, seed=c["seed"])
     B, eps = dev(s.B), dev(s.eps)
     _, _, r64 = ccsd.solve(B, eps, o)
-    _, _, rmx = ccsd.solve(B, eps, o, ppl_precision="bf16x3", tol=1e-8, tol_energy=1e-9)
-    print("E fp64", r64.e_corr, "E bf16x3", rmx.e_corr, "diff", rmx.e_corr - r64.e_corr, flush=True)
+    _, _, rmx = ccsd.solve(B, eps, o, ppl_precision=precision, tol=1e-8, tol_energy=1e-9)
+    print("E fp64", r64.e_corr, f"E {precision}", rmx.e_corr, "diff", rmx.e_corr - r64.e_corr, flush=True)
     assert r64.converged and rmx.converged
     assert abs(rmx.e_corr - r64.e_corr) <= 1e-6
