@@ -9,6 +9,8 @@
 // loop).  Contractions with few output tiles and a long k range are split over k
 // into partial products that a second kernel sums in a fixed order, so the result
 // does not depend on scheduling.
+#include <cstdlib>
+
 #include "gemm.h"
 
 namespace ri {
@@ -159,6 +161,130 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, int a_kfast, 
     }
 }
 
+// Large tiles for large contractions whose innermost summed extent K3 is a multiple
+// of KC: a chunk of KC summed indices then never crosses a level boundary, so its
+// offset is one wave-uniform base plus dk * stride.  Tile 128 x 128, four waves in
+// a 2 x 2 arrangement, each wave 64 x 64 (4 x 4 MFMA tiles).  grid (ceil(N/128),
+// ceil(M/128), batch), no split.
+constexpr int BL = 128;
+template <int a_kfast, int b_kfast>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_f64_large(GemmDesc g) {
+  __shared__ double sA[2][KC][BL + 2];
+  __shared__ double sB[2][KC][BL + 2];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const long bm = static_cast<long>(blockIdx.y) * BL, bn = static_cast<long>(blockIdx.x) * BL;
+  const long zb = blockIdx.z;
+  const double* A = g.a + zb * g.a_batch;
+  const double* B = g.b + zb * g.b_batch;
+
+  // element r of this thread: (row, dk) of the 128 x 16 tile; k-fast operands put
+  // 16 consecutive lanes on consecutive k, the others 64 lanes on consecutive rows
+  // (row, dk) of element r; recomputed where used rather than kept in registers
+#define A_ROW(r) (a_kfast ? (t >> 4) + 16 * (r) : (t & 127))
+#define A_K(r) (a_kfast ? (t & 15) : (t >> 7) + 2 * (r))
+#define B_ROW(r) (b_kfast ? (t >> 4) + 16 * (r) : (t & 127))
+#define B_K(r) (b_kfast ? (t & 15) : (t >> 7) + 2 * (r))
+  long aoff[8], boff[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const long m = bm + A_ROW(r), n = bn + B_ROW(r);
+    aoff[r] = m < g.M ? (m / g.M2) * g.am1 + (m % g.M2) * g.am2 + A_K(r) * g.ak3 : -1;
+    boff[r] = n < g.N ? (n / g.N2) * g.bn1 + (n % g.N2) * g.bn2 + B_K(r) * g.bk3 : -1;
+  }
+  // wave-uniform position of the chunk base in (k1, k2, k3) and its offsets
+  long k2 = 0, k3 = 0, ka = 0, kb = 0;
+  const long nchunks = g.K / KC;
+
+  double4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  const int l16 = lane & 15, kq = lane >> 4;
+  double ra[8], rb[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    ra[r] = aoff[r] >= 0 ? A[aoff[r]] : 0.0;
+    rb[r] = boff[r] >= 0 ? B[boff[r]] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    sA[0][A_K(r)][A_ROW(r)] = ra[r];
+    sB[0][B_K(r)][B_ROW(r)] = rb[r];
+  }
+  __syncthreads();
+  for (long ch = 0; ch < nchunks; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nchunks;
+    if (more) {
+      // advance the base by KC (never past a K3 boundary inside the chunk)
+      k3 += KC;
+      ka += KC * g.ak3;
+      kb += KC * g.bk3;
+      if (k3 == g.K3) {
+        k3 = 0;
+        ka += g.ak2 - g.K3 * g.ak3;
+        kb += g.bk2 - g.K3 * g.bk3;
+        if (++k2 == g.K2) {
+          k2 = 0;
+          ka += g.ak1 - g.K2 * g.ak2;
+          kb += g.bk1 - g.K2 * g.bk2;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        ra[r] = aoff[r] >= 0 ? A[aoff[r] + ka] : 0.0;
+        rb[r] = boff[r] >= 0 ? B[boff[r] + kb] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < KC / 4; ++s4) {
+      const int kk = 4 * s4 + kq;
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sA[buf][kk][wm + 16 * i + l16];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sB[buf][kk][wn + 16 * j + l16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        sA[buf ^ 1][A_K(r)][A_ROW(r)] = ra[r];
+        sB[buf ^ 1][B_K(r)][B_ROW(r)] = rb[r];
+      }
+    }
+    __syncthreads();
+  }
+  // D[4r + lane/16][lane%16] in element r
+  double* C = g.c + zb * g.c_batch;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long n = bn + wn + 16 * j + l16;
+      if (n >= g.N) continue;
+      const long cn = (n / g.N2) * g.cn1 + (n % g.N2) * g.cn2;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long m = bm + wm + 16 * i + 4 * r + kq;
+        if (m >= g.M) continue;
+        double* p = C + (m / g.M2) * g.cm1 + (m % g.M2) * g.cm2 + cn;
+        const double val = g.alpha * acc[i][j][r];
+        *p = g.beta == 0.0 ? val : val + g.beta * *p;
+      }
+    }
+}
+
+#undef A_ROW
+#undef A_K
+#undef B_ROW
+#undef B_K
+
 // C(m, n) = alpha * sum_z part[z][m][n] + beta * C(m, n), z in order
 __global__ void split_reduce(GemmDesc g, int splits, const double* __restrict__ part) {
   const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -192,6 +318,21 @@ int run(const GemmDesc& g, int batch, double* scratch, size_t scratch_len, hipSt
   // consecutive threads walk k when the innermost k stride is 1 and the m/n stride is not
   const int a_kfast = (g.ak3 == 1 && g.K3 >= 4 && g.am2 != 1) ? 1 : 0;
   const int b_kfast = (g.bk3 == 1 && g.K3 >= 4 && g.bn2 != 1) ? 1 : 0;
+  // large tiles when they still give the chip a few workgroups per CU
+  // (RI_GEMM_LARGE_MIN_TILES overrides the threshold, e.g. to test the path at small sizes)
+  const char* env = getenv("RI_GEMM_LARGE_MIN_TILES");
+  const long env_tiles = env ? strtol(env, nullptr, 10) : 0;
+  const long min_tiles = env_tiles > 0 ? env_tiles : 256;
+  const long tiles_l = ((g.M + BL - 1) / BL) * ((g.N + BL - 1) / BL) * batch;
+  if (g.K3 % KC == 0 && tiles_l >= min_tiles) {
+    dim3 grid(static_cast<unsigned>((g.N + BL - 1) / BL), static_cast<unsigned>((g.M + BL - 1) / BL),
+              static_cast<unsigned>(batch));
+    if (a_kfast && b_kfast) gemm_f64_large<1, 1><<<grid, 256, 0, s>>>(g);
+    else if (a_kfast) gemm_f64_large<1, 0><<<grid, 256, 0, s>>>(g);
+    else if (b_kfast) gemm_f64_large<0, 1><<<grid, 256, 0, s>>>(g);
+    else gemm_f64_large<0, 0><<<grid, 256, 0, s>>>(g);
+    return check_launch("gemm_f64_large");
+  }
   const size_t want = scratch_doubles(g, batch);
   int splits = 1;
   if (want > 0 && scratch && scratch_len >= want) splits = static_cast<int>(want / (static_cast<size_t>(g.M) * g.N));

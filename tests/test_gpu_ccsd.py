@@ -157,3 +157,17 @@ def test_learned_guess_option_matches_guess_then_user_start():
     assert ra.converged and rb.converged and ra.iterations == rb.iterations
     assert ra.e_corr == rb.e_corr and bool((ta == tb).all())
     assert np.isnan(rb.e_mp2)
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(3, 32, 40, 870), (5, 48, 37, 871), (2, 64, 64, 872)])
+def test_residual_parity_large_tile_contractions(o, v, naux, seed, monkeypatch):
+    """v a multiple of 16 with the large-tile threshold lowered to one tile, so every
+    contraction whose innermost summed extent allows it runs on the 128 x 128 kernel."""
+    monkeypatch.setenv("RI_GEMM_LARGE_MIN_TILES", "1")
+    s = draw_system(o, v, naux, seed=seed, scale=0.2)
+    t1 = draw_matrix((o, v), seed + 2, 0.05)
+    t2 = draw_pair_symmetric(o, v, seed + 3, 0.05)
+    om1, om2 = _cc().residual(dev(s.B), dev(s.eps), o, dev(t1), dev(t2))
+    r1, r2 = oc.residual(s.B, s.eps, o, t1, t2)
+    assert rel_max(host(om1), r1) <= 1e-11
+    assert rel_max(host(om2), r2) <= 1e-11
