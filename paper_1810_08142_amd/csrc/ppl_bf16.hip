@@ -72,6 +72,13 @@ __device__ inline f32x4_t mfma3_mirror(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf
   return mfma_bf16(ah, bh, c);
 }
 
+// LDS swizzles.  A ds_read_b128 is conflict-free when every group of 8 lanes
+// (32 banks) -- or of 16 lanes (64 banks) -- covers distinct 16-byte bank groups.
+// Build: a row e of 4 runs; run r of row e is stored at r ^ sw4(e).  Contraction:
+// a row of 8 runs (hi/lo x 4); run q of row m is stored at q ^ sw8(m).
+__host__ __device__ inline int sw4(int e) { return ((e >> 1) ^ (e >> 2)) & 3; }
+__host__ __device__ inline int sw8(int m) { return (m ^ (m >> 3)) & 7; }
+
 // slot (0..255) of a cd block pair -> (c_in, d_in)
 __host__ __device__ inline void slot_cd(int slot, int& c_in, int& d_in) {
   const int q = slot >> 6, w = (slot >> 3) & 7, i = (slot >> 2) & 1, j = slot & 3;
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(256) void pack_tau_bf16_kernel(const double* __rest
 // Same decomposition as the FP64 build: one workgroup = ab block pair x one quarter
 // (8 c by 8 d) of a cd block pair; wave w owns c in {2(w>>1), +1}, d in {4(w&1)..+3}.
 // LDS per buffer: 16-byte runs [x 16][hl 2][e 32][run 4], run index XOR-swizzled with
-// (e>>2)&3 so the 16 lanes reading one run column hit distinct banks.
+// sw4(e) so that the lanes of one ds_read_b128 hit distinct banks.
 // grid (nbp*4, slab_pairs), block 512
 __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
                                                       int Qp, int vp, long slab0, long K, int want_minus,
@@ -176,11 +183,11 @@ __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict
     const int cg = x < 8 ? c_base + x : d_base + (x - 8);
     const int ag = e < 16 ? Ab * TB + e : Bb * TB + (e - 16);
     goff[r] = (static_cast<size_t>(cg) * vp + ag) * Qp + run * 8;
-    loff[r] = ((x * 2 + hl_t) * 32 + e) * 4 + (run ^ ((e >> 2) & 3));
+    loff[r] = ((x * 2 + hl_t) * 32 + e) * 4 + (run ^ sw4(e));
   }
   // fragment addresses (run indices) for this lane
   const int fe = lane & 15, frun = lane >> 4;
-  const int fsw = frun ^ ((fe >> 2) & 3);  // same swizzle for e and e + 16
+  const int fsw = frun ^ sw4(fe);  // same swizzle for e and e + 16 (sw4 reads bits 1..3)
   const int xc0 = (w >> 1) * 2, xd0 = 8 + (w & 1) * 4;
 
   f32x4_t o1[2][4], o2[2][4];
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict
 // ---------------------------------------------------------------- contract
 // C[m][n] = sum_k W[m][k] T[n][k] (both split); tile 128 (m) x 16*NTW (n); four waves,
 // wave w owns rows 32w..32w+31 (two m tiles) and all columns.  LDS holds 16-byte runs
-// [row][hl 2][run 4], run index swizzled with (row>>2)&3.
+// [row][8 runs: hl 2 x run 4], run index XOR-swizzled with sw8(row).
 // grid (ncol/(16*NTW), rows/128), block 256
 template <int NTW>
 __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
@@ -301,7 +308,7 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
     const int row = id >> 3, hl = (id >> 2) & 1, run = id & 3;
     asrc[r] = hl ? Wl : Wh;
     aoff[r] = static_cast<size_t>(m0 + row) * K + run * 8;
-    alo[r] = (row * 2 + hl) * 4 + (run ^ ((row >> 2) & 3));
+    alo[r] = row * 8 + ((hl * 4 + run) ^ sw8(row));
   }
   size_t boff[BPER];
   int blo[BPER];
@@ -312,10 +319,9 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
     const int row = (id >> 3) < BN ? (id >> 3) : 0, hl = (id >> 2) & 1, run = id & 3;
     bsrc[r] = hl ? Tl : Th;
     boff[r] = static_cast<size_t>(n0 + row) * K + run * 8;
-    blo[r] = id < BRUNS ? (row * 2 + hl) * 4 + (run ^ ((row >> 2) & 3)) : -1;
+    blo[r] = id < BRUNS ? row * 8 + ((hl * 4 + run) ^ sw8(row)) : -1;
   }
   const int fr = lane & 15, frun = lane >> 4;
-  const int fsw = frun ^ ((fr >> 2) & 3);
 
   f32x4_t acc[2][NTW];
 #pragma unroll
@@ -351,12 +357,15 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int hl = 0; hl < 2; ++hl)
-        a[i][hl] = __builtin_bit_cast(bf16x8_t, sA[ab + ((w * 32 + i * 16 + fr) * 2 + hl) * 4 + fsw]);
+      for (int hl = 0; hl < 2; ++hl) {
+        const int row = w * 32 + i * 16 + fr;
+        a[i][hl] = __builtin_bit_cast(bf16x8_t, sA[ab + row * 8 + ((hl * 4 + frun) ^ sw8(row))]);
+      }
 #pragma unroll
     for (int u = 0; u < NTW; ++u) {
-      const bf16x8_t bh = __builtin_bit_cast(bf16x8_t, sB[bb + ((u * 16 + fr) * 2 + 0) * 4 + fsw]);
-      const bf16x8_t bl = __builtin_bit_cast(bf16x8_t, sB[bb + ((u * 16 + fr) * 2 + 1) * 4 + fsw]);
+      const int row = u * 16 + fr, sw = sw8(row);
+      const bf16x8_t bh = __builtin_bit_cast(bf16x8_t, sB[bb + row * 8 + ((0 * 4 + frun) ^ sw)]);
+      const bf16x8_t bl = __builtin_bit_cast(bf16x8_t, sB[bb + row * 8 + ((1 * 4 + frun) ^ sw)]);
 #pragma unroll
       for (int i = 0; i < 2; ++i) acc[i][u] = mfma3(a[i][0], a[i][1], bh, bl, acc[i][u]);
     }
