@@ -82,6 +82,19 @@ int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double
 int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
               int precision, void* ws, size_t ws_bytes, void* stream);
 
+/* One shard of a ladder call split over several devices: the split of the virtual
+ * index a across domains of Sec. II.D, at the granularity of the (ab) block-pair
+ * slabs.  Shard k of n (0 <= k < n) builds and contracts the slabs k, k + n,
+ * k + 2n, ... and accumulates only their (a, b) entries of R; every device holds
+ * full replicas of B_vv and tau and packs all of tau.  The n shards together add
+ * exactly (bitwise) what one ri_ppl_ex call adds, since every R entry comes from
+ * one slab; a multi-device caller sums or gathers the shards' R.  The slab size
+ * depends only on (o, v, naux, precision) and RI_PPL_W_BYTES / RI_PPL_SLAB_PAIRS,
+ * which must agree across the shards.  ri_ppl_ex is shard 0 of 1.
+ * RI_E_ARG for an invalid (shard, nshards). */
+int ri_ppl_shard(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
+                 int precision, int shard, int nshards, void* ws, size_t ws_bytes, void* stream);
+
 /* Workspace bytes ri_ppl_ex needs for these sizes (0 on invalid arguments). */
 size_t ri_ppl_workspace_bytes(int o, int v, int naux, int precision);
 

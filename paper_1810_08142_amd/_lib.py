@@ -51,6 +51,8 @@ _SIGS = [
     ("ri_last_hip_error", _c.c_int, []),
     ("ri_ppl", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _dp]),
     ("ri_ppl_ex", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _c.c_int, _dp, _c.c_size_t, _dp]),
+    ("ri_ppl_shard", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _c.c_int, _c.c_int, _c.c_int, _dp,
+                                _c.c_size_t, _dp]),
     ("ri_ppl_workspace_bytes", _c.c_size_t, [_c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_build_tau", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _dp, _dp]),

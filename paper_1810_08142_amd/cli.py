@@ -3,12 +3,16 @@
   python -m paper_1810_08142_amd.cli ccsd --config c5 [--scale verbatim|naux] [--precision fp64|bf16x3]
                                         [--polish 1e-6] [--check-fp64] [--model net.bin]
   python -m paper_1810_08142_amd.cli ttc --config c3 --scale naux [--polish 1e-6]
+  python -m paper_1810_08142_amd.cli shard --config c4 --nshards 8 [--precision fp64|fp32|bf16x3]
 
 `ccsd` prints one JSON line with the report (energy, iterations, timings, scale
 used).  `ttc` (time to converged E_corr) solves one system three times -- FP64
 ladder, mixed ladder, mixed ladder with FP64 polish -- and prints one JSON line per
 run with its E_corr error against the FP64 run and the FP64 residual of its final
-amplitudes.
+amplitudes.  `shard` times every shard k of n of one ladder call (ri_ppl_shard, the
+per-device work of an n-device split over the (ab) slabs) one after another and prints
+the slowest and mean shard, with the R bytes one device would contribute to the
+all-gather that completes the call.
 """
 from __future__ import annotations
 
@@ -42,9 +46,15 @@ def main(argv=None):
     t.add_argument("--tol", type=float, default=1e-8)
     t.add_argument("--tol-energy", type=float, default=1e-9)
     t.add_argument("--verbose", action="store_true")
+    sh = sub.add_parser("shard")
+    sh.add_argument("--config", default="c4")
+    sh.add_argument("--nshards", type=int, default=8)
+    sh.add_argument("--precision", default="fp64")
     args = ap.parse_args(argv)
     if args.cmd == "ttc":
         return _ttc(args)
+    if args.cmd == "shard":
+        return _shard(args)
 
     import torch
 
@@ -107,6 +117,44 @@ def _ttc(args):
         print(json.dumps(out), flush=True)
         rc = rc or (0 if rep.converged else 3)
     return rc
+
+
+def _shard(args):
+    import torch
+
+    from . import ccsd, ppl
+    from .synthetic import CONFIGS, draw_system
+    cfg = CONFIGS[args.config]
+    s = draw_system(cfg["o"], cfg["v"], cfg["naux"], seed=cfg["seed"])
+    o, v, naux = s.o, s.v, s.naux
+    B = torch.from_numpy(s.B).to("cuda")
+    eps = torch.from_numpy(s.eps).to("cuda")
+    t1 = torch.from_numpy(s.t1).to("cuda")
+    del s
+    t2, _ = ccsd.mp2_guess(B, eps, o)
+    tau = ppl.build_tau(t1, t2)
+    B_vv = B[:, o:, o:].contiguous()
+    del B, t2
+    R = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    ppl.ppl(B_vv, tau, R, precision=args.precision, shard=(0, args.nshards))  # warm-up
+    torch.cuda.synchronize()
+    ms = []
+    for k in range(args.nshards):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ppl.ppl(B_vv, tau, R, precision=args.precision, shard=(k, args.nshards))
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        print(json.dumps(dict(shard=k, ms=ms[-1])), file=sys.stderr, flush=True)
+    flops = ppl.flops(o, v, naux)
+    out = dict(config=args.config, o=o, v=v, naux=naux, precision=args.precision, nshards=args.nshards,
+               shard_ms=ms, max_shard_ms=max(ms), mean_shard_ms=sum(ms) / len(ms), sum_ms=sum(ms),
+               imbalance=max(ms) / (sum(ms) / len(ms)),
+               tflops_per_device_at_max=flops / args.nshards / (max(ms) * 1e-3) / 1e12,
+               r_bytes_per_device=8.0 * o * o * v * v / args.nshards)
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 if __name__ == "__main__":

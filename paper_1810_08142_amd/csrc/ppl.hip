@@ -562,7 +562,7 @@ static void launch_contract(int ntw, const typename KS::T* W, const typename KS:
 
 template <class KS>
 static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const double* tau, double* R, void* ws,
-                    hipStream_t s) {
+                    int shard, int nshards, hipStream_t s) {
   typedef typename KS::T T;
   Carve cv(ws, p.bytes);
   T* Bc = cv.take<T>(p.n_Bc);
@@ -591,6 +591,7 @@ static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const d
     }
   }
   for (long slab0 = 0; slab0 < p.nbp; slab0 += p.slab_bp) {
+    if ((slab0 / p.slab_bp) % nshards != shard) continue;  // another shard's slab
     const long npairs = (p.nbp - slab0) < p.slab_bp ? (p.nbp - slab0) : p.slab_bp;
     const long M = npairs * 256;
     double le, lt;
@@ -621,11 +622,11 @@ static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const d
 
 // Runs the FP64 or FP32 path of plan p on workspace ws (allocated when null).
 static int run_typed(const Plan& p, int precision, const double* B_vv, long qs, long rs, const double* tau,
-                     double* R, void* ws, hipStream_t s) {
+                     double* R, void* ws, int shard, int nshards, hipStream_t s) {
   void* buf = ws;
   if (!buf) RI_TRY(dev_alloc(&buf, p.bytes, s));
-  const int rc = precision == RI_PREC_FP32 ? run_plan<K32>(p, B_vv, qs, rs, tau, R, buf, s)
-                                           : run_plan<K64>(p, B_vv, qs, rs, tau, R, buf, s);
+  const int rc = precision == RI_PREC_FP32 ? run_plan<K32>(p, B_vv, qs, rs, tau, R, buf, shard, nshards, s)
+                                           : run_plan<K64>(p, B_vv, qs, rs, tau, R, buf, shard, nshards, s);
   if (!ws) dev_free(buf, s);
   return rc;
 }
@@ -636,7 +637,7 @@ static size_t esize_of(int precision) { return precision == RI_PREC_FP32 ? 4 : 8
 
 int ppl_strided(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
                 int precision, hipStream_t s) {
-  if (precision == RI_PREC_BF16X3) return ppl::bf16x3_run(B, qs, rs, tau, o, v, naux, R, nullptr, 0, s);
+  if (precision == RI_PREC_BF16X3) return ppl::bf16x3_run(B, qs, rs, tau, o, v, naux, R, nullptr, 0, 0, 1, s);
   if (precision != RI_PREC_FP64 && precision != RI_PREC_FP32) {
     set_error("ladder: unknown precision %d", precision);
     return RI_E_ARG;
@@ -646,7 +647,7 @@ int ppl_strided(const double* B, long qs, long rs, const double* tau, int o, int
     set_error("ladder: invalid sizes o=%d v=%d naux=%d", o, v, naux);
     return RI_E_ARG;
   }
-  return ppl::run_typed(p, precision, B, qs, rs, tau, R, nullptr, s);
+  return ppl::run_typed(p, precision, B, qs, rs, tau, R, nullptr, 0, 1, s);
 }
 
 }  // namespace ri
@@ -670,9 +671,13 @@ double ri_ppl_flops(int o, int v, int naux) {
   return static_cast<double>(naux) * dv * dv * dv * (dv + 1) + 2.0 * (pv * pv * po + pvm * pvm * pom);
 }
 
-int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R, int precision,
-              void* ws, size_t ws_bytes, void* stream) {
+int ri_ppl_shard(const double* B_vv, const double* tau, int o, int v, int naux, double* R, int precision,
+                 int shard, int nshards, void* ws, size_t ws_bytes, void* stream) {
   clear_error();
+  if (nshards < 1 || shard < 0 || shard >= nshards) {
+    set_error("ri_ppl: shard %d of %d is not a valid shard", shard, nshards);
+    return RI_E_ARG;
+  }
   if (!B_vv || !tau || !R) {
     set_error("ri_ppl: null pointer argument");
     return RI_E_ARG;
@@ -703,12 +708,17 @@ int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, dou
     return RI_E_ARG;
   }
   if (precision == RI_PREC_BF16X3)
-    return ppl::bf16x3_run(B_vv, static_cast<long>(v) * v, v, tau, o, v, naux, R, ws, ws_bytes, s);
+    return ppl::bf16x3_run(B_vv, static_cast<long>(v) * v, v, tau, o, v, naux, R, ws, ws_bytes, shard, nshards, s);
   if (ws && ws_bytes < p.bytes) {
     set_error("ri_ppl: workspace of %zu bytes is smaller than the %zu required", ws_bytes, p.bytes);
     return RI_E_NOMEM;
   }
-  return ppl::run_typed(p, precision, B_vv, static_cast<long>(v) * v, v, tau, R, ws, s);
+  return ppl::run_typed(p, precision, B_vv, static_cast<long>(v) * v, v, tau, R, ws, shard, nshards, s);
+}
+
+int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R, int precision,
+              void* ws, size_t ws_bytes, void* stream) {
+  return ri_ppl_shard(B_vv, tau, o, v, naux, R, precision, 0, 1, ws, ws_bytes, stream);
 }
 
 int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream) {

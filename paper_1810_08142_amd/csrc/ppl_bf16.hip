@@ -466,7 +466,7 @@ size_t bf16x3_workspace_bytes(int o, int v, int naux) {
 }
 
 int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R, void* ws,
-               size_t ws_bytes, hipStream_t s) {
+               size_t ws_bytes, int shard, int nshards, hipStream_t s) {
   MPlan p;
   if (!make_mplan(o, v, naux, p)) {
     set_error("ladder: invalid sizes o=%d v=%d naux=%d", o, v, naux);
@@ -515,6 +515,7 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
       }
     }
     for (long slab0 = 0; slab0 < p.nbp && rc == RI_OK; slab0 += p.slab_bp) {
+      if ((slab0 / p.slab_bp) % nshards != shard) continue;  // another shard's slab
       const long npairs = std::min(p.slab_bp, p.nbp - slab0);
       const long M = npairs * 256;
       double le, lt;

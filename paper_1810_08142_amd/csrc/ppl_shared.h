@@ -90,7 +90,7 @@ void launch_unpack_f32(const float* S, const float* A, int NP, int NM, int o, in
 // Mixed-precision ladder (split-bf16, three products, FP32 accumulation).
 size_t bf16x3_workspace_bytes(int o, int v, int naux);
 int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
-               void* ws, size_t ws_bytes, hipStream_t s);
+               void* ws, size_t ws_bytes, int shard, int nshards, hipStream_t s);
 
 }  // namespace ppl
 }  // namespace ri

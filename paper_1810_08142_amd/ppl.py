@@ -35,8 +35,9 @@ def _need(t: torch.Tensor, name: str, shape, dtype=torch.float64):
 
 
 def ppl(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, precision="fp64",
-        workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """R += sum_cd (ac|bd) tau^{cd}_{ij}; B_vv [naux][v][v], tau and R [o][o][v][v]."""
+        workspace: torch.Tensor | None = None, stream=None, shard=None) -> torch.Tensor:
+    """R += sum_cd (ac|bd) tau^{cd}_{ij}; B_vv [naux][v][v], tau and R [o][o][v][v].
+    ``shard=(k, n)`` adds only shard k of n of the (ab) slabs (ri_ppl_shard)."""
     naux, v = B_vv.shape[0], B_vv.shape[1]
     o = tau.shape[0]
     _need(B_vv, "B_vv", (naux, v, v))
@@ -49,8 +50,9 @@ def ppl(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, precision="fp64"
         if not workspace.is_cuda or not workspace.is_contiguous():
             raise ValueError("workspace must be a contiguous device tensor")
         ws, nbytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
-    rc = L.ri_ppl_ex(B_vv.data_ptr(), tau.data_ptr(), o, v, naux, R.data_ptr(), _prec(precision),
-                     ws, nbytes, _stream(stream))
+    k, n = (0, 1) if shard is None else shard
+    rc = L.ri_ppl_shard(B_vv.data_ptr(), tau.data_ptr(), o, v, naux, R.data_ptr(), _prec(precision),
+                        int(k), int(n), ws, nbytes, _stream(stream))
     _lib.check(rc, "ri_ppl")
     return R
 

@@ -193,3 +193,28 @@ def test_c4_full_size_sampled_fp64_and_mixed():
     err = np.abs(got["bf16x3"] - ref)
     print("c4 bf16x3 max rel err", float(err.max() / np.abs(ref).max()), flush=True)
     assert bool(np.all(err <= bound))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_shards_add_up_to_the_whole_call(precision, monkeypatch):
+    """Shards k of n of the (ab) slabs together add bitwise what one call adds."""
+    import torch
+    monkeypatch.setenv("RI_PPL_SLAB_PAIRS", "2")
+    o, v, naux = 3, 70, 18  # 15 block pairs -> 8 slabs of at most 2
+    s = draw_system(o, v, naux, seed=941)
+    tau = draw_pair_symmetric(o, v, 942)
+    B, T = dev(s.B_vv), dev(tau)
+    full = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    _ppl().ppl(B, T, full, precision=precision)
+    total = torch.zeros_like(full)
+    for k in range(3):
+        part = torch.zeros_like(full)
+        _ppl().ppl(B, T, part, precision=precision, shard=(k, 3))
+        assert float(part.abs().max()) > 0.0
+        # shards touch disjoint entries
+        assert not bool(((total != 0) & (part != 0)).any())
+        total += part
+    assert bool((total == full).all())
+    from paper_1810_08142_amd import _lib
+    with pytest.raises(_lib.RIError):
+        _ppl().ppl(B, T, full, precision=precision, shard=(3, 3))
