@@ -196,49 +196,55 @@ __device__ __forceinline__ void build_body(const T* __restrict__ Bc, int naux_p,
   const int xc0 = (w >> 1) * 2, xd0 = 8 + (w & 1) * 4;
   const int m = lane & 15, kq = lane >> 4;
   const int nchunks = naux_p / KC;
-  vec_t stage[NV];
+  // In a diagonal cd block pair the quarter with c in the upper and d in the lower
+  // half holds only c > d slots, whose packed amplitudes are zero: its W entries are
+  // written as zeros without the build (uniform over the workgroup).
+  const bool skip = Cb == Db && quarter == 2;
+  if (!skip) {
+    vec_t stage[NV];
 #pragma unroll
-  for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r]);
+    for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r]);
 #pragma unroll
-  for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(lds0 + loff[r]) = stage[r];
-  __syncthreads();
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const int buf = ch & 1;
-    const bool more = ch + 1 < nchunks;
-    if (more) {
-      const size_t qo = static_cast<size_t>(ch + 1) * qstride;
+    for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(lds0 + loff[r]) = stage[r];
+    __syncthreads();
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const int buf = ch & 1;
+      const bool more = ch + 1 < nchunks;
+      if (more) {
+        const size_t qo = static_cast<size_t>(ch + 1) * qstride;
 #pragma unroll
-      for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r] + qo);
-    }
-#pragma unroll
-    for (int s = 0; s < KC / 4; ++s) {
-      const int kk = 4 * s + kq;
-      T a_c[2], b_c[2], a_d[4], b_d[4];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a_c[i] = lds[buf][xc0 + i][kk][m];
-        b_c[i] = lds[buf][xc0 + i][kk][16 + m];
+        for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r] + qo);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        a_d[j] = lds[buf][xd0 + j][kk][m];
-        b_d[j] = lds[buf][xd0 + j][kk][16 + m];
-      }
+      for (int s = 0; s < KC / 4; ++s) {
+        const int kk = 4 * s + kq;
+        T a_c[2], b_c[2], a_d[4], b_d[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i) {
+          a_c[i] = lds[buf][xc0 + i][kk][m];
+          b_c[i] = lds[buf][xc0 + i][kk][16 + m];
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          acc1[i][j] = MF::mma(a_c[i], b_d[j], acc1[i][j]);  // (ac|bd)
-          acc2[i][j] = MF::mma(a_d[j], b_c[i], acc2[i][j]);  // (ad|bc)
+          a_d[j] = lds[buf][xd0 + j][kk][m];
+          b_d[j] = lds[buf][xd0 + j][kk][16 + m];
         }
-    }
-    if (more) {
-      T* dst = lds0 + (buf ^ 1) * LBUF;
 #pragma unroll
-      for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(dst + loff[r]) = stage[r];
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            acc1[i][j] = MF::mma(a_c[i], b_d[j], acc1[i][j]);  // (ac|bd)
+            acc2[i][j] = MF::mma(a_d[j], b_c[i], acc2[i][j]);  // (ad|bc)
+          }
+      }
+      if (more) {
+        T* dst = lds0 + (buf ^ 1) * LBUF;
+#pragma unroll
+        for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(dst + loff[r]) = stage[r];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  }  // !skip
 
   // epilogue: W+-[slot][ab slot]; element r of a lane is row a_in = drow(r, lane),
   // column b_in = lane & 15 of the (a, b) tile.

@@ -200,49 +200,53 @@ __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict
     }
 
   const int nsteps = Qp / QC;
-  u32x4_t stage[8];
+  // the c > d quarter of a diagonal cd block pair carries zero amplitudes: zeros only
+  const bool skip = Cb == Db && quarter == 2;
+  if (!skip) {
+    u32x4_t stage[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const u32x4_t*>(src + goff[r]);
+    for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const u32x4_t*>(src + goff[r]);
 #pragma unroll
-  for (int r = 0; r < 8; ++r) lds[loff[r]] = stage[r];
-  __syncthreads();
-  for (int st = 0; st < nsteps; ++st) {
-    const int base = (st & 1) * RUNS;
-    const bool more = st + 1 < nsteps;
-    if (more) {
-      const size_t qo = static_cast<size_t>(st + 1) * QC;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const u32x4_t*>(src + goff[r] + qo);
-    }
-    auto frag = [&](int x, int hl, int e_off) -> bf16x8_t {
-      const u32x4_t v = lds[base + ((x * 2 + hl) * 32 + e_off + fe) * 4 + fsw];
-      return __builtin_bit_cast(bf16x8_t, v);
-    };
-    bf16x8_t ac[2][2], bc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int hl = 0; hl < 2; ++hl) {
-        ac[i][hl] = frag(xc0 + i, hl, 0);
-        bc[i][hl] = frag(xc0 + i, hl, 16);
-      }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const bf16x8_t adh = frag(xd0 + j, 0, 0), adl = frag(xd0 + j, 1, 0);
-      const bf16x8_t bdh = frag(xd0 + j, 0, 16), bdl = frag(xd0 + j, 1, 16);
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        o1[i][j] = mfma3(ac[i][0], ac[i][1], bdh, bdl, o1[i][j]);  // (ac|bd)
-        o2[i][j] = mfma3_mirror(adh, adl, bc[i][0], bc[i][1], o2[i][j]);  // (ad|bc)
-      }
-    }
-    if (more) {
-      const int nb = ((st + 1) & 1) * RUNS;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) lds[nb + loff[r]] = stage[r];
-    }
+    for (int r = 0; r < 8; ++r) lds[loff[r]] = stage[r];
     __syncthreads();
-  }
+    for (int st = 0; st < nsteps; ++st) {
+      const int base = (st & 1) * RUNS;
+      const bool more = st + 1 < nsteps;
+      if (more) {
+        const size_t qo = static_cast<size_t>(st + 1) * QC;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const u32x4_t*>(src + goff[r] + qo);
+      }
+      auto frag = [&](int x, int hl, int e_off) -> bf16x8_t {
+        const u32x4_t v = lds[base + ((x * 2 + hl) * 32 + e_off + fe) * 4 + fsw];
+        return __builtin_bit_cast(bf16x8_t, v);
+      };
+      bf16x8_t ac[2][2], bc[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl) {
+          ac[i][hl] = frag(xc0 + i, hl, 0);
+          bc[i][hl] = frag(xc0 + i, hl, 16);
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bf16x8_t adh = frag(xd0 + j, 0, 0), adl = frag(xd0 + j, 1, 0);
+        const bf16x8_t bdh = frag(xd0 + j, 0, 16), bdl = frag(xd0 + j, 1, 16);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          o1[i][j] = mfma3(ac[i][0], ac[i][1], bdh, bdl, o1[i][j]);  // (ac|bd)
+          o2[i][j] = mfma3_mirror(adh, adl, bc[i][0], bc[i][1], o2[i][j]);  // (ad|bc)
+        }
+      }
+      if (more) {
+        const int nb = ((st + 1) & 1) * RUNS;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) lds[nb + loff[r]] = stage[r];
+      }
+      __syncthreads();
+    }
+  }  // !skip
 
   // epilogue: lane holds (a_in = 4*(lane>>4) + r, b_in = lane&15) for the wave's 8 slots
   const size_t slot0 = static_cast<size_t>(pcd) * 256 + quarter * 64 + w * 8;
