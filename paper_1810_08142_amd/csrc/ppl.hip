@@ -278,10 +278,12 @@ __global__ __launch_bounds__(512) void build_w_f32(const float* __restrict__ Bc,
 
 // ---------------------------------------------------------------- 3b. contract
 // C[m][n] = sum_k W[k][m] T[k][n];  tile 64 (m) x 16*NTW (n); 4 waves, wave w owns
-// rows 16w..16w+15 and all columns.  grid (ncol/(16*NTW), M/64), block 256
+// rows 16w..16w+15 and all columns.  The k range may be split over grid.z: split z
+// sums k in [z*kz, min(K, (z+1)*kz)) into C + z*zs, and the unpack adds the splits in
+// order.  grid (ncol/(16*NTW), M/64, splits), block 256
 template <class T, int NTW>
 __device__ __forceinline__ void contract_body(const T* __restrict__ W, const T* __restrict__ Tt, long K, long M,
-                                              int ncol, T* __restrict__ C) {
+                                              int ncol, T* __restrict__ C, long kz, long zs) {
   // W rows have stride M (the slab width); C has NTW*16*gridDim.x columns
   typedef Mfma<T> MF;
   typedef typename MF::vec_t vec_t;
@@ -295,6 +297,13 @@ __device__ __forceinline__ void contract_body(const T* __restrict__ W, const T* 
   xcd_tile(tx, ty);
   const long n0 = static_cast<long>(tx) * BN, m0 = static_cast<long>(ty) * 64;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  {  // this split's k range (every split holds at least one chunk)
+    const long k_lo = blockIdx.z * kz;
+    K = (K < k_lo + kz ? K : k_lo + kz) - k_lo;
+    W += k_lo * M;
+    Tt += k_lo * ncol;
+    C += blockIdx.z * zs;
+  }
 
   // staging offsets (computed once; the chunk loop adds k0 * row stride)
   long aoff[NA], boff[NTW];
@@ -367,22 +376,25 @@ __device__ __forceinline__ void contract_body(const T* __restrict__ W, const T* 
 }
 template <int NTW>
 __global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W, const double* __restrict__ Tt,
-                                                    long K, long M, int ncol, double* __restrict__ C) {
-  contract_body<double, NTW>(W, Tt, K, M, ncol, C);
+                                                    long K, long M, int ncol, double* __restrict__ C, long kz,
+                                                    long zs) {
+  contract_body<double, NTW>(W, Tt, K, M, ncol, C, kz, zs);
 }
 template <int NTW>
 __global__ __launch_bounds__(256) void contract_f32(const float* __restrict__ W, const float* __restrict__ Tt,
-                                                    long K, long M, int ncol, float* __restrict__ C) {
-  contract_body<float, NTW>(W, Tt, K, M, ncol, C);
+                                                    long K, long M, int ncol, float* __restrict__ C, long kz,
+                                                    long zs) {
+  contract_body<float, NTW>(W, Tt, K, M, ncol, C, kz, zs);
 }
 
 // ---------------------------------------------------------------- 3c. unpack
-// S and A are FP64 (FP64 path) or FP32 (mixed paths); R accumulates in FP64.
-// grid (slab_pairs, ceil(po/16)), block 256
+// S and A are FP64 (FP64 path) or FP32 (mixed paths); R accumulates in FP64.  S and
+// A may come as zp (zm) partial sums over k, zs (zsm) elements apart, added here in
+// order.  grid (slab_pairs, ceil(po/16)), block 256
 template <class T>
 __global__ __launch_bounds__(256) void unpack_kernel(const T* __restrict__ S, const T* __restrict__ A,
                                                      int NP, int NM, int o, int v, long slab0,
-                                                     double* __restrict__ R) {
+                                                     double* __restrict__ R, int zp, long zsp, int zm, long zsm) {
   __shared__ double sS[256][NG + 1];
   __shared__ double sA[256][NG + 1];
   int Ab, Bb;
@@ -397,8 +409,12 @@ __global__ __launch_bounds__(256) void unpack_kernel(const T* __restrict__ S, co
     if (lam < po) {
       int i, j;
       tri_decode(lam, i, j);
-      s = static_cast<double>(S[(row0 + slot) * NP + lam]);
-      if (i < j) x = static_cast<double>(A[(row0 + slot) * NM + j * (j - 1) / 2 + i]);
+      const size_t is = (row0 + slot) * NP + lam;
+      for (int z = 0; z < zp; ++z) s += static_cast<double>(S[z * zsp + is]);
+      if (i < j) {
+        const size_t ia = (row0 + slot) * NM + j * (j - 1) / 2 + i;
+        for (int z = 0; z < zm; ++z) x += static_cast<double>(A[z * zsm + ia]);
+      }
     }
     sS[slot][cc] = s;
     sA[slot][cc] = x;
@@ -434,8 +450,9 @@ __global__ __launch_bounds__(256) void unpack_kernel(const T* __restrict__ S, co
 }
 
 void launch_unpack_f32(const float* S, const float* A, int NP, int NM, int o, int v, long slab0, long npairs,
-                       double* R, hipStream_t s) {
-  unpack_kernel<float><<<dim3(npairs, (o * (o + 1) / 2 + NG - 1) / NG), 256, 0, s>>>(S, A, NP, NM, o, v, slab0, R);
+                       double* R, int zp, long zsp, int zm, long zsm, hipStream_t s) {
+  unpack_kernel<float><<<dim3(npairs, (o * (o + 1) / 2 + NG - 1) / NG), 256, 0, s>>>(S, A, NP, NM, o, v, slab0, R,
+                                                                                  zp, zsp, zm, zsm);
 }
 
 // ---------------------------------------------------------------- tau
@@ -458,9 +475,32 @@ struct Plan {
   int po, pm, NP, NM, ntw_p, ntw_m;
   long slab_bp, slab_M;
   size_t esize;  // bytes per element of the staged operands (8 FP64, 4 FP32)
+  long zrows_p, zrows_m;  // largest splits x rows of one contraction launch (sizes S and A)
   size_t n_Bc, n_Tp, n_Tm, n_W, n_S, n_A;
   size_t bytes;
 };
+
+// Splits of the contraction's k range for a launch of `rows` rows and 16*ntw-wide
+// column tiles: enough workgroups to fill the chip about three deep (the kernel's
+// occupancy), at least 32 chunks per split.  kz: summed indices per split.
+static int contract_splits(int ncol, int ntw, long rows, long K, long& kz) {
+  const long nwg = (ncol / (16 * ntw)) * (rows / 64);
+  long z = (3 * 256 + nwg - 1) / nwg;
+  z = std::max(1L, std::min(z, K / (32 * KC)));
+  kz = (K + z - 1) / z;
+  kz = (kz + KC - 1) / KC * KC;
+  return static_cast<int>((K + kz - 1) / kz);
+}
+
+// Largest splits x rows over the slab sizes of plan p (the full slab and the last).
+static long max_split_rows(const Plan& p, int ncol, int ntw) {
+  if (ncol == 0) return 0;
+  long kz;
+  const long last = p.nbp - (p.nbp - 1) / p.slab_bp * p.slab_bp;
+  long best = 0;
+  for (long rows : {p.slab_M, last * 256}) best = std::max(best, contract_splits(ncol, ntw, rows, p.K, kz) * rows);
+  return best;
+}
 
 static bool make_plan(int o, int v, int naux, size_t esize, Plan& p) {
   if (o <= 0 || v <= 0 || naux <= 0) return false;
@@ -492,8 +532,10 @@ static bool make_plan(int o, int v, int naux, size_t esize, Plan& p) {
   p.n_Tp = static_cast<size_t>(p.K) * p.NP;
   p.n_Tm = static_cast<size_t>(p.K) * p.NM;
   p.n_W = static_cast<size_t>(p.K) * p.slab_M;
-  p.n_S = static_cast<size_t>(p.slab_M) * p.NP;
-  p.n_A = static_cast<size_t>(p.slab_M) * p.NM;
+  p.zrows_p = max_split_rows(p, p.NP, p.ntw_p);
+  p.zrows_m = max_split_rows(p, p.NM, p.ntw_m);
+  p.n_S = static_cast<size_t>(p.zrows_p) * p.NP;
+  p.n_A = static_cast<size_t>(p.zrows_m) * p.NM;
   size_t b = 0;
   for (size_t n : {p.n_Bc, p.n_Tp, p.n_Tm, p.n_W, p.pm > 0 ? p.n_W : 0, p.n_S, p.n_A})
     b = round_up(b, 256) + n * esize;
@@ -520,8 +562,9 @@ struct K64 {
     build_w_f64<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, Wp, Wm);
   }
   template <int NTW>
-  static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C) {
-    contract_f64<NTW><<<g, 256, 0, s>>>(W, Tt, K, M, ncol, C);
+  static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C, long kz,
+                         long zs) {
+    contract_f64<NTW><<<g, 256, 0, s>>>(W, Tt, K, M, ncol, C, kz, zs);
   }
 };
 struct K32 {
@@ -542,27 +585,30 @@ struct K32 {
     build_w_f32<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, Wp, Wm);
   }
   template <int NTW>
-  static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C) {
-    contract_f32<NTW><<<g, 256, 0, s>>>(W, Tt, K, M, ncol, C);
+  static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C, long kz,
+                         long zs) {
+    contract_f32<NTW><<<g, 256, 0, s>>>(W, Tt, K, M, ncol, C, kz, zs);
   }
 };
 
-// rows: number of C rows (multiple of 64) computed; ldw: row stride of W
+// rows: number of C rows (multiple of 64) computed; ldw: row stride of W.  The k
+// range is split `splits` ways (kz each) into partial outputs rows*ncol apart.
 template <class KS>
 static void launch_contract(int ntw, const typename KS::T* W, const typename KS::T* Tt, long K, long ldw, long rows,
-                            int ncol, typename KS::T* C, hipStream_t s) {
-  const unsigned gy = static_cast<unsigned>(rows / 64);
+                            int ncol, typename KS::T* C, int splits, long kz, hipStream_t s) {
+  const unsigned gy = static_cast<unsigned>(rows / 64), gz = static_cast<unsigned>(splits);
+  const long zs = rows * ncol;
   switch (ntw) {
-    case 1: KS::template contract_k<1>(dim3(ncol / 16, gy), s, W, Tt, K, ldw, ncol, C); break;
-    case 2: KS::template contract_k<2>(dim3(ncol / 32, gy), s, W, Tt, K, ldw, ncol, C); break;
-    case 3: KS::template contract_k<3>(dim3(ncol / 48, gy), s, W, Tt, K, ldw, ncol, C); break;
-    case 4: KS::template contract_k<4>(dim3(ncol / 64, gy), s, W, Tt, K, ldw, ncol, C); break;
-    case 5: KS::template contract_k<5>(dim3(ncol / 80, gy), s, W, Tt, K, ldw, ncol, C); break;
-    case 6: KS::template contract_k<6>(dim3(ncol / 96, gy), s, W, Tt, K, ldw, ncol, C); break;
-    case 7: KS::template contract_k<7>(dim3(ncol / 112, gy), s, W, Tt, K, ldw, ncol, C); break;
-    case 8: KS::template contract_k<8>(dim3(ncol / 128, gy), s, W, Tt, K, ldw, ncol, C); break;
-    case 9: KS::template contract_k<9>(dim3(ncol / 144, gy), s, W, Tt, K, ldw, ncol, C); break;
-    default: KS::template contract_k<10>(dim3(ncol / 160, gy), s, W, Tt, K, ldw, ncol, C); break;
+    case 1: KS::template contract_k<1>(dim3(ncol / 16, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
+    case 2: KS::template contract_k<2>(dim3(ncol / 32, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
+    case 3: KS::template contract_k<3>(dim3(ncol / 48, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
+    case 4: KS::template contract_k<4>(dim3(ncol / 64, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
+    case 5: KS::template contract_k<5>(dim3(ncol / 80, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
+    case 6: KS::template contract_k<6>(dim3(ncol / 96, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
+    case 7: KS::template contract_k<7>(dim3(ncol / 112, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
+    case 8: KS::template contract_k<8>(dim3(ncol / 128, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
+    case 9: KS::template contract_k<9>(dim3(ncol / 144, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
+    default: KS::template contract_k<10>(dim3(ncol / 160, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
   }
 }
 
@@ -602,6 +648,9 @@ static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const d
     const long M = npairs * 256;
     double le, lt;
     count_pairs(p.v, slab0, npairs, le, lt);
+    long kzp = 0, kzm = 0;
+    const int zp = contract_splits(p.NP, p.ntw_p, M, p.K, kzp);
+    const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, p.K, kzm) : 1;
     {
       // per valid (a <= b): the v x v matrix (ac|bd) over all c, d, naux products each
       ProfScope ps(s, KS::build, 2.0 * p.naux * vv * le);
@@ -610,16 +659,17 @@ static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const d
     }
     {
       ProfScope ps(s, KS::contract, 2.0 * (le * pv * p.po + lt * pvm * p.pm));
-      launch_contract<KS>(p.ntw_p, Wp, Tp, p.K, p.slab_M, M, p.NP, S, s);
+      launch_contract<KS>(p.ntw_p, Wp, Tp, p.K, p.slab_M, M, p.NP, S, zp, kzp, s);
       RI_TRY(check_launch(KS::contract));
       if (p.pm > 0) {
-        launch_contract<KS>(p.ntw_m, Wm, Tm, p.K, p.slab_M, M, p.NM, A, s);
+        launch_contract<KS>(p.ntw_m, Wm, Tm, p.K, p.slab_M, M, p.NM, A, zm, kzm, s);
         RI_TRY(check_launch(KS::contract));
       }
     }
     {
       ProfScope ps(s, KS::unpack, 0.0, 16.0 * oo * (le + lt));
-      unpack_kernel<T><<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R);
+      unpack_kernel<T><<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R, zp,
+                                                                        M * p.NP, zm, M * p.NM);
       RI_TRY(check_launch(KS::unpack));
     }
   }

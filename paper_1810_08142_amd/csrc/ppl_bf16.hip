@@ -286,12 +286,13 @@ __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict
 // ---------------------------------------------------------------- contract
 // C[m][n] = sum_k W[m][k] T[n][k] (both split); tile 128 (m) x 16*NTW (n); four waves,
 // wave w owns rows 32w..32w+31 (two m tiles) and all columns.  LDS holds 16-byte runs
-// [row][8 runs: hl 2 x run 4], run index XOR-swizzled with sw8(row).
-// grid (ncol/(16*NTW), rows/128), block 256
+// [row][8 runs: hl 2 x run 4], run index XOR-swizzled with sw8(row).  The k range may
+// be split over grid.z: split z sums k in [z*kz, min(K, (z+1)*kz)) into C + z*zs.
+// grid (ncol/(16*NTW), rows/128, splits), block 256
 template <int NTW>
 __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
                                                        const uint16_t* __restrict__ Th, const uint16_t* __restrict__ Tl,
-                                                       long K, int ncol, float* __restrict__ C) {
+                                                       long K, int ncol, float* __restrict__ C, long kz, long zs) {
   constexpr int BN = 16 * NTW;
   constexpr int ARUNS = CBM * 2 * 4, BRUNS = BN * 2 * 4;
   __shared__ u32x4_t sA[2 * ARUNS];
@@ -300,6 +301,10 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
   xcd_tile(tx, ty);
   const long n0 = static_cast<long>(tx) * BN, m0 = static_cast<long>(ty) * CBM;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  // this split's k range (every split holds at least one step)
+  const long k_lo = blockIdx.z * kz;
+  const long k_len = (K < k_lo + kz ? K : k_lo + kz) - k_lo;
+  C += blockIdx.z * zs;
 
   // staging: A 1024 runs (4 per thread), B 8*BN runs (ceil(BN/32) per thread)
   constexpr int BPER = (BRUNS + 255) / 256;
@@ -311,7 +316,7 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
     const int id = t + 256 * r;
     const int row = id >> 3, hl = (id >> 2) & 1, run = id & 3;
     asrc[r] = hl ? Wl : Wh;
-    aoff[r] = static_cast<size_t>(m0 + row) * K + run * 8;
+    aoff[r] = static_cast<size_t>(m0 + row) * K + k_lo + run * 8;
     alo[r] = row * 8 + ((hl * 4 + run) ^ sw8(row));
   }
   size_t boff[BPER];
@@ -322,7 +327,7 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
     const int id = t + 256 * r;
     const int row = (id >> 3) < BN ? (id >> 3) : 0, hl = (id >> 2) & 1, run = id & 3;
     bsrc[r] = hl ? Tl : Th;
-    boff[r] = static_cast<size_t>(n0 + row) * K + run * 8;
+    boff[r] = static_cast<size_t>(n0 + row) * K + k_lo + run * 8;
     blo[r] = id < BRUNS ? row * 8 + ((hl * 4 + run) ^ sw8(row)) : -1;
   }
   const int fr = lane & 15, frun = lane >> 4;
@@ -333,7 +338,7 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
 #pragma unroll
     for (int u = 0; u < NTW; ++u) acc[i][u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-  const long nsteps = K / KB;
+  const long nsteps = k_len / KB;
   u32x4_t ra[4], rb[BPER];
 #pragma unroll
   for (int r = 0; r < 4; ++r) ra[r] = *reinterpret_cast<const u32x4_t*>(asrc[r] + aoff[r]);
@@ -396,14 +401,37 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
 }
 
 // ---------------------------------------------------------------- host
+// Splits of the contraction's k range for a launch of `rows` rows and 16*ntw-wide
+// column tiles: enough workgroups to fill the chip about two deep (the kernel's
+// occupancy), at least 32 steps per split.  kz: summed indices per split.
+static int contract_splits(int ncol, int ntw, long rows, long K, long& kz) {
+  const long nwg = (ncol / (16 * ntw)) * (rows / CBM);
+  long z = (2 * 256 + nwg - 1) / nwg;
+  z = std::max(1L, std::min(z, K / (32 * KB)));
+  kz = (K + z - 1) / z;
+  kz = (kz + KB - 1) / KB * KB;
+  return static_cast<int>((K + kz - 1) / kz);
+}
+
 struct MPlan {
   int o, v, naux, nb, vp, Qp;
   long nbp, K;
   int po, pm, NP, NM, ntw_p, ntw_m;
   long slab_bp, slab_M;
   size_t n_B, n_Tp, n_Tm, n_W, n_S, n_A;  // element counts
+  long zrows_p, zrows_m;                   // largest splits x rows of one contraction launch
   size_t bytes;
 };
+
+// Largest splits x rows over the slab sizes of plan p (the full slab and the last).
+static long max_split_rows(const MPlan& p, int ncol, int ntw) {
+  if (ncol == 0) return 0;
+  long kz;
+  const long last = p.nbp - (p.nbp - 1) / p.slab_bp * p.slab_bp;
+  long best = 0;
+  for (long rows : {p.slab_M, last * 256}) best = std::max(best, contract_splits(ncol, ntw, rows, p.K, kz) * rows);
+  return best;
+}
 
 static bool make_mplan(int o, int v, int naux, MPlan& p) {
   if (o <= 0 || v <= 0 || naux <= 0 || o > 4096 || v > 65536 || naux > (1 << 24)) return false;
@@ -431,8 +459,10 @@ static bool make_mplan(int o, int v, int naux, MPlan& p) {
   p.n_Tp = static_cast<size_t>(p.NP) * p.K;
   p.n_Tm = static_cast<size_t>(p.NM) * p.K;
   p.n_W = static_cast<size_t>(p.slab_M) * p.K;
-  p.n_S = static_cast<size_t>(p.slab_M) * p.NP;
-  p.n_A = static_cast<size_t>(p.slab_M) * p.NM;
+  p.zrows_p = max_split_rows(p, p.NP, p.ntw_p);
+  p.zrows_m = max_split_rows(p, p.NM, p.ntw_m);
+  p.n_S = static_cast<size_t>(p.zrows_p) * p.NP;
+  p.n_A = static_cast<size_t>(p.zrows_m) * p.NM;
   size_t b = 0;
   // 16-bit: Bh, Bl, Tph, Tpl, Tmh, Tml, Wph, Wpl, Wmh, Wml; 32-bit: S, A
   for (size_t n : {p.n_B, p.n_B, p.n_Tp, p.n_Tp, p.n_Tm, p.n_Tm, p.n_W, p.n_W, p.pm > 0 ? p.n_W : 0,
@@ -443,24 +473,26 @@ static bool make_mplan(int o, int v, int naux, MPlan& p) {
   return true;
 }
 
+// The k range is split `splits` ways (kz each) into partial outputs rows*ncol apart.
 template <int NTW>
 static void launch_c(const uint16_t* Wh, const uint16_t* Wl, const uint16_t* Th, const uint16_t* Tl, long K,
-                     long rows, int ncol, float* C, hipStream_t s) {
-  contract_bf16x3<NTW><<<dim3(ncol / (16 * NTW), rows / CBM), 256, 0, s>>>(Wh, Wl, Th, Tl, K, ncol, C);
+                     long rows, int ncol, float* C, int splits, long kz, hipStream_t s) {
+  contract_bf16x3<NTW><<<dim3(ncol / (16 * NTW), rows / CBM, splits), 256, 0, s>>>(Wh, Wl, Th, Tl, K, ncol, C, kz,
+                                                                                   rows * ncol);
 }
 
 static void launch_contract(int ntw, const uint16_t* Wh, const uint16_t* Wl, const uint16_t* Th, const uint16_t* Tl,
-                            long K, long rows, int ncol, float* C, hipStream_t s) {
+                            long K, long rows, int ncol, float* C, int splits, long kz, hipStream_t s) {
   switch (ntw) {
-    case 1: launch_c<1>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
-    case 2: launch_c<2>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
-    case 3: launch_c<3>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
-    case 4: launch_c<4>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
-    case 5: launch_c<5>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
-    case 6: launch_c<6>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
-    case 7: launch_c<7>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
-    case 8: launch_c<8>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
-    default: launch_c<9>(Wh, Wl, Th, Tl, K, rows, ncol, C, s); break;
+    case 1: launch_c<1>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
+    case 2: launch_c<2>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
+    case 3: launch_c<3>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
+    case 4: launch_c<4>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
+    case 5: launch_c<5>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
+    case 6: launch_c<6>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
+    case 7: launch_c<7>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
+    case 8: launch_c<8>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
+    default: launch_c<9>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
   }
 }
 
@@ -524,6 +556,9 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
       const long M = npairs * 256;
       double le, lt;
       count_pairs(v, slab0, npairs, le, lt);
+      long kzp = 0, kzm = 0;
+      const int zp = contract_splits(p.NP, p.ntw_p, M, p.K, kzp);
+      const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, p.K, kzm) : 1;
       {
         ProfScope ps(s, "build_w_bf16x3", 2.0 * naux * vv * le);
         build_w_bf16x3<<<dim3(p.nbp * 4, npairs), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K, p.pm > 0 ? 1 : 0,
@@ -532,16 +567,16 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
       }
       {
         ProfScope ps(s, "contract_bf16x3", 2.0 * (le * pv * p.po + lt * pvm * p.pm));
-        launch_contract(p.ntw_p, Wph, Wpl, Tph, Tpl, p.K, M, p.NP, S, s);
+        launch_contract(p.ntw_p, Wph, Wpl, Tph, Tpl, p.K, M, p.NP, S, zp, kzp, s);
         if ((rc = check_launch("contract_bf16x3(+)"))) break;
         if (p.pm > 0) {
-          launch_contract(p.ntw_m, Wmh, Wml, Tmh, Tml, p.K, M, p.NM, A, s);
+          launch_contract(p.ntw_m, Wmh, Wml, Tmh, Tml, p.K, M, p.NM, A, zm, kzm, s);
           if ((rc = check_launch("contract_bf16x3(-)"))) break;
         }
       }
       {
         ProfScope ps(s, "unpack_f32", 0.0, 16.0 * oo * (le + lt));
-        launch_unpack_f32(S, A, p.NP, p.NM, o, v, slab0, npairs, R, s);
+        launch_unpack_f32(S, A, p.NP, p.NM, o, v, slab0, npairs, R, zp, M * p.NP, zm, M * p.NM, s);
         if ((rc = check_launch("unpack_f32"))) break;
       }
     }

@@ -84,8 +84,9 @@ inline void count_pairs(int v, long p0, long n, double& le, double& lt) {
 }
 
 // R += mirrored S +- A from FP32 slab results (shared unpack kernel).
+// S, A: zp (zm) partial sums over k, zsp (zsm) elements apart, added in order.
 void launch_unpack_f32(const float* S, const float* A, int NP, int NM, int o, int v, long slab0, long npairs,
-                       double* R, hipStream_t s);
+                       double* R, int zp, long zsp, int zm, long zsm, hipStream_t s);
 
 // Mixed-precision ladder (split-bf16, three products, FP32 accumulation).
 size_t bf16x3_workspace_bytes(int o, int v, int naux);
