@@ -143,13 +143,14 @@ typedef struct ri_ccsd_opts {
   int guess;           /* RI_GUESS_MP2, RI_GUESS_USER or RI_GUESS_MLP */
   int verbose;         /* one line per iteration on stderr */
   /* Mixed-precision ladder only: once max |Omega| <= polish_residual, every later
-   * residual uses the FP64 ladder, and convergence is only declared on an FP64
-   * residual (0 disables; default 0). */
+   * residual uses the polish_precision ladder, and convergence is only declared on
+   * such a residual (0 disables; default 0). */
   double polish_residual;
   /* Mixed-precision ladder only: evaluate max |Omega| of the returned amplitudes
    * once more with the FP64 ladder into rep->residual_inf_fp64 (default 0). */
   int check_fp64;
   ri_mlp* mlp; /* network for RI_GUESS_MLP (default NULL) */
+  int polish_precision; /* ladder after the polish switch: RI_PREC_FP64 (default) or RI_PREC_FP32 */
 } ri_ccsd_opts;
 
 typedef struct ri_ccsd_report {
@@ -165,7 +166,7 @@ typedef struct ri_ccsd_report {
    * residual_inf when the last residual used it (converged FP64 or polished runs),
    * NaN when not evaluated */
   double residual_inf_fp64;
-  int polish_iteration; /* first iteration whose residual used the FP64 ladder after a
+  int polish_iteration; /* first iteration whose residual used the polish ladder after a
                            mixed start (-1: none) */
   double seconds_guess; /* wall time until the guess and its energy were ready */
 } ri_ccsd_report;

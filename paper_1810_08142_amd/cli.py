@@ -6,10 +6,10 @@
   python -m paper_1810_08142_amd.cli shard --config c4 --nshards 8 [--precision fp64|fp32|bf16x3]
 
 `ccsd` prints one JSON line with the report (energy, iterations, timings, scale
-used).  `ttc` (time to converged E_corr) solves one system three times -- FP64
-ladder, mixed ladder, mixed ladder with FP64 polish -- and prints one JSON line per
-run with its E_corr error against the FP64 run and the FP64 residual of its final
-amplitudes.  `shard` times every shard k of n of one ladder call (ri_ppl_shard, the
+used).  `ttc` (time to converged E_corr) solves one system four times -- FP64
+ladder, mixed ladder, mixed ladder with FP64 polish, mixed ladder with FP32 polish --
+and prints one JSON line per run with its E_corr error against the FP64 run and the
+FP64 residual of its final amplitudes.  `shard` times every shard k of n of one ladder call (ri_ppl_shard, the
 per-device work of an n-device split over the (ab) slabs) one after another and prints
 the slowest and mean shard, with the R bytes one device would contribute to the
 all-gather that completes the call.
@@ -35,6 +35,7 @@ def main(argv=None):
     c.add_argument("--diis", type=int, default=6)
     c.add_argument("--verbose", action="store_true")
     c.add_argument("--polish", type=float, default=0.0)
+    c.add_argument("--polish-precision", default="fp64")
     c.add_argument("--check-fp64", action="store_true")
     c.add_argument("--model", default="")
     t = sub.add_parser("ttc")
@@ -75,7 +76,8 @@ def main(argv=None):
     try:
         t1, t2, rep = ccsd.solve(B, eps, s.o, max_iter=args.max_iter, tol=args.tol, tol_energy=args.tol_energy,
                                  diis_size=args.diis, ppl_precision=args.precision, verbose=args.verbose,
-                                 polish_residual=args.polish, check_fp64=args.check_fp64, mlp=net)
+                                 polish_residual=args.polish, check_fp64=args.check_fp64, mlp=net,
+                                 polish_precision=args.polish_precision)
     except RIError as e:
         print(json.dumps(dict(config=args.config, scale=s.scale, precision=args.precision, error=str(e))), flush=True)
         return 4
@@ -99,16 +101,19 @@ def _ttc(args):
     B = torch.from_numpy(s.B).to("cuda")
     eps = torch.from_numpy(s.eps).to("cuda")
     torch.cuda.synchronize()
-    runs = [("fp64", "fp64", 0.0), ("mixed", args.mixed, 0.0), ("mixed+polish", args.mixed, args.polish)]
+    runs = [("fp64", "fp64", 0.0, "fp64"), ("mixed", args.mixed, 0.0, "fp64"),
+            ("mixed+polish", args.mixed, args.polish, "fp64"), ("mixed+fp32 polish", args.mixed, args.polish, "fp32")]
     ref = None
     rc = 0
-    for name, prec, pol in runs:
+    for name, prec, pol, pprec in runs:
         _, _, rep = ccsd.solve(B, eps, s.o, max_iter=args.max_iter, tol=args.tol, tol_energy=args.tol_energy,
-                               ppl_precision=prec, polish_residual=pol, check_fp64=True, verbose=args.verbose)
+                               ppl_precision=prec, polish_residual=pol, check_fp64=True, verbose=args.verbose,
+                               polish_precision=pprec)
         if ref is None:
             ref = rep
         out = dict(config=args.config, o=s.o, v=s.v, naux=s.naux, seed=s.seed, scale=s.scale, run=name,
-                   precision=prec, polish_residual=pol, tol=args.tol, tol_energy=args.tol_energy,
+                   precision=prec, polish_residual=pol, polish_precision=pprec, tol=args.tol,
+                   tol_energy=args.tol_energy,
                    converged=rep.converged, iterations=rep.iterations, polish_iteration=rep.polish_iteration,
                    e_corr=rep.e_corr, delta_e_vs_fp64=rep.e_corr - ref.e_corr,
                    residual_inf=rep.residual_inf, residual_inf_fp64=rep.residual_inf_fp64,

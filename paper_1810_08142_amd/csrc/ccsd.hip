@@ -425,6 +425,7 @@ void ri_ccsd_default_opts(ri_ccsd_opts* op) {
   op->polish_residual = 0.0;
   op->check_fp64 = 0;
   op->mlp = nullptr;
+  op->polish_precision = RI_PREC_FP64;
 }
 
 int ri_mp2_guess(const ri_system* sys, double* t1, double* t2, double* e_mp2, void* stream) {
@@ -493,13 +494,15 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
   if (opts) op = *opts;
   else ri_ccsd_default_opts(&op);
   if (op.max_iter < 0 || op.diis_size > 16 || op.guess < RI_GUESS_MP2 || op.guess > RI_GUESS_MLP ||
-      !(op.polish_residual >= 0.0) || (op.guess == RI_GUESS_MLP && !op.mlp)) {
+      !(op.polish_residual >= 0.0) || (op.guess == RI_GUESS_MLP && !op.mlp) ||
+      (op.polish_precision != RI_PREC_FP64 && op.polish_precision != RI_PREC_FP32)) {
     set_error("ri_ccsd_iterate: invalid options (max_iter %d, diis_size %d, guess %d, polish %g, mlp %p)",
               op.max_iter, op.diis_size, op.guess, op.polish_residual, static_cast<void*>(op.mlp));
     return RI_E_ARG;
   }
   const bool mixed = op.ppl_precision != RI_PREC_FP64;
-  const bool polish = mixed && op.polish_residual > 0.0;
+  const bool polish = mixed && op.polish_residual > 0.0 && op.polish_precision != op.ppl_precision;
+  const int final_prec = polish ? op.polish_precision : op.ppl_precision;
   const int slots = op.diis_size >= 2 ? op.diis_size : 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
   cc::Ctx c(sys, s);
@@ -544,21 +547,21 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
     rrms = std::sqrt(hostv[1] / static_cast<double>(nt));
     if (op.verbose)
       fprintf(stderr, "[ccsd] iter %3d  E = %.12f  |Omega|inf = %.3e  ladder %s %.1f ms\n", it, e, rinf,
-              prec == RI_PREC_FP64 ? "fp64" : "mixed", ms_ppl);
+              prec == RI_PREC_FP64 ? "fp64" : prec == RI_PREC_FP32 ? "fp32" : "bf16x3", ms_ppl);
     if (!std::isfinite(rinf) || !std::isfinite(e) || rinf > 1e8) {
       set_error("ri_ccsd_iterate: non-finite or divergent residual at iteration %d", it);
       status = RI_E_NUMERIC;
       break;
     }
-    const bool on_fp64 = prec == RI_PREC_FP64;
-    if (it > 0 && rinf <= op.tol_residual && std::fabs(e - e_prev) <= op.tol_energy && (on_fp64 || !polish)) {
+    const bool on_final = prec == final_prec;
+    if (it > 0 && rinf <= op.tol_residual && std::fabs(e - e_prev) <= op.tol_energy && on_final) {
       conv = true;
       break;
     }
-    // switch to the FP64 ladder for the remaining residuals (the step below still
+    // switch to the polish ladder for the remaining residuals (the step below still
     // uses this mixed residual)
-    if (polish && !on_fp64 && rinf <= op.polish_residual) {
-      prec = RI_PREC_FP64;
+    if (polish && !on_final && rinf <= op.polish_residual) {
+      prec = final_prec;
       polish_it = it + 1;
     }
     // Jacobi step into the next history slot

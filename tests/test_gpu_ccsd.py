@@ -171,3 +171,18 @@ def test_residual_parity_large_tile_contractions(o, v, naux, seed, monkeypatch):
     r1, r2 = oc.residual(s.B, s.eps, o, t1, t2)
     assert rel_max(host(om1), r1) <= 1e-11
     assert rel_max(host(om2), r2) <= 1e-11
+
+
+def test_mixed_ladder_with_fp32_polish():
+    c = CONFIGS["c1"]
+    o = c["o"]
+    s = draw_system(o, c["v"], c["naux"], seed=c["seed"])
+    B, eps = dev(s.B), dev(s.eps)
+    _, _, r64 = _cc().solve(B, eps, o, tol=1e-10, tol_energy=1e-10)
+    _, _, rp = _cc().solve(B, eps, o, ppl_precision="bf16x3", polish_residual=1e-6, polish_precision="fp32",
+                           tol=1e-9, tol_energy=1e-10, check_fp64=True)
+    print("fp64", r64, "fp32-polished", rp, flush=True)
+    assert rp.converged and rp.polish_iteration > 0
+    # converged on an FP32-ladder residual; the FP64 residual of the result is evaluated
+    assert np.isfinite(rp.residual_inf_fp64) and rp.residual_inf_fp64 <= 1e-7
+    assert abs(rp.e_corr - r64.e_corr) <= 1e-8
