@@ -142,15 +142,21 @@ typedef struct ri_ccsd_opts {
   int ppl_precision;   /* RI_PREC_* of the ladder term (default RI_PREC_FP64) */
   int guess;           /* RI_GUESS_MP2, RI_GUESS_USER or RI_GUESS_MLP */
   int verbose;         /* one line per iteration on stderr */
-  /* Mixed-precision ladder only: once max |Omega| <= polish_residual, every later
-   * residual uses the polish_precision ladder, and convergence is only declared on
-   * such a residual (0 disables; default 0). */
+  /* Reduced precision only (ladder or other_precision): once max |Omega| <=
+   * polish_residual, every later residual uses the polish_precision ladder (and FP64
+   * other contractions when that is FP64), and convergence is only declared on such
+   * a residual (0 disables; default 0). */
   double polish_residual;
-  /* Mixed-precision ladder only: evaluate max |Omega| of the returned amplitudes
-   * once more with the FP64 ladder into rep->residual_inf_fp64 (default 0). */
+  /* Reduced precision only: evaluate max |Omega| of the returned amplitudes once more
+   * in FP64 throughout into rep->residual_inf_fp64 (default 0). */
   int check_fp64;
   ri_mlp* mlp; /* network for RI_GUESS_MLP (default NULL) */
   int polish_precision; /* ladder after the polish switch: RI_PREC_FP64 (default) or RI_PREC_FP32 */
+  /* Arithmetic of the large non-ladder contractions (the o^3 v^3 terms and the
+   * integral builds from the dressed factors): RI_PREC_FP64 (default) or RI_PREC_FP32
+   * (operands rounded to FP32, FP32 MFMA).  Setup, update, DIIS and energy stay FP64;
+   * an FP64 polish also returns these contractions to FP64. */
+  int other_precision;
 } ri_ccsd_opts;
 
 typedef struct ri_ccsd_report {

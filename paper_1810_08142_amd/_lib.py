@@ -30,7 +30,8 @@ class RICcsdOpts(_c.Structure):
     _fields_ = [("max_iter", _c.c_int), ("tol_residual", _c.c_double), ("tol_energy", _c.c_double),
                 ("diis_size", _c.c_int), ("diis_start", _c.c_int), ("ppl_precision", _c.c_int),
                 ("guess", _c.c_int), ("verbose", _c.c_int), ("polish_residual", _c.c_double),
-                ("check_fp64", _c.c_int), ("mlp", _c.c_void_p), ("polish_precision", _c.c_int)]
+                ("check_fp64", _c.c_int), ("mlp", _c.c_void_p), ("polish_precision", _c.c_int),
+                ("other_precision", _c.c_int)]
 
 
 class RICcsdReport(_c.Structure):

@@ -76,12 +76,13 @@ class Report:
 
 def solve(B, eps, o, t1=None, t2=None, max_iter=100, tol=1e-10, tol_energy=1e-10, diis_size=6,
           diis_start=2, ppl_precision="fp64", verbose=False, stream=None, raise_on_noconv=False,
-          polish_residual=0.0, check_fp64=False, mlp=None, polish_precision="fp64"):
+          polish_residual=0.0, check_fp64=False, mlp=None, polish_precision="fp64", other_precision="fp64"):
     """Jacobi + DIIS from the MP2 guess, from t1/t2 when given, or from the learned
     guess of `mlp` (a paper_1810_08142_amd.mlp.Net).  With a mixed-precision ladder,
     `polish_residual` > 0 switches the ladder to `polish_precision` (FP64 or FP32) once
     max |Omega| falls below it,
     and `check_fp64` evaluates the FP64 residual of the final amplitudes.
+    `other_precision` "fp32" runs the large non-ladder contractions on the FP32 MFMA.
     Returns (t1, t2, Report); t1/t2 passed in are overwritten."""
     sy = _system(B, eps, o)
     v = sy.v
@@ -93,6 +94,7 @@ def solve(B, eps, o, t1=None, t2=None, max_iter=100, tol=1e-10, tol_energy=1e-10
     op.verbose = 1 if verbose else 0
     op.polish_residual = float(polish_residual)
     op.polish_precision = _prec(polish_precision)
+    op.other_precision = _prec(other_precision)
     op.check_fp64 = 1 if check_fp64 else 0
     if mlp is not None and t2 is not None:
         raise ValueError("pass either a network or starting amplitudes, not both")

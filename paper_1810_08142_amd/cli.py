@@ -36,6 +36,7 @@ def main(argv=None):
     c.add_argument("--verbose", action="store_true")
     c.add_argument("--polish", type=float, default=0.0)
     c.add_argument("--polish-precision", default="fp64")
+    c.add_argument("--other-precision", default="fp64")
     c.add_argument("--check-fp64", action="store_true")
     c.add_argument("--model", default="")
     t = sub.add_parser("ttc")
@@ -43,6 +44,7 @@ def main(argv=None):
     t.add_argument("--scale", default="naux")
     t.add_argument("--mixed", default="bf16x3")
     t.add_argument("--polish", type=float, default=1e-6)
+    t.add_argument("--other", default="fp64", help="precision of the other large contractions in the mixed runs")
     t.add_argument("--max-iter", type=int, default=100)
     t.add_argument("--tol", type=float, default=1e-8)
     t.add_argument("--tol-energy", type=float, default=1e-9)
@@ -77,7 +79,7 @@ def main(argv=None):
         t1, t2, rep = ccsd.solve(B, eps, s.o, max_iter=args.max_iter, tol=args.tol, tol_energy=args.tol_energy,
                                  diis_size=args.diis, ppl_precision=args.precision, verbose=args.verbose,
                                  polish_residual=args.polish, check_fp64=args.check_fp64, mlp=net,
-                                 polish_precision=args.polish_precision)
+                                 polish_precision=args.polish_precision, other_precision=args.other_precision)
     except RIError as e:
         print(json.dumps(dict(config=args.config, scale=s.scale, precision=args.precision, error=str(e))), flush=True)
         return 4
@@ -101,18 +103,19 @@ def _ttc(args):
     B = torch.from_numpy(s.B).to("cuda")
     eps = torch.from_numpy(s.eps).to("cuda")
     torch.cuda.synchronize()
-    runs = [("fp64", "fp64", 0.0, "fp64"), ("mixed", args.mixed, 0.0, "fp64"),
-            ("mixed+polish", args.mixed, args.polish, "fp64"), ("mixed+fp32 polish", args.mixed, args.polish, "fp32")]
+    runs = [("fp64", "fp64", 0.0, "fp64", "fp64"), ("mixed", args.mixed, 0.0, "fp64", args.other),
+            ("mixed+polish", args.mixed, args.polish, "fp64", args.other),
+            ("mixed+fp32 polish", args.mixed, args.polish, "fp32", args.other)]
     ref = None
     rc = 0
-    for name, prec, pol, pprec in runs:
+    for name, prec, pol, pprec, oprec in runs:
         _, _, rep = ccsd.solve(B, eps, s.o, max_iter=args.max_iter, tol=args.tol, tol_energy=args.tol_energy,
                                ppl_precision=prec, polish_residual=pol, check_fp64=True, verbose=args.verbose,
-                               polish_precision=pprec)
+                               polish_precision=pprec, other_precision=oprec)
         if ref is None:
             ref = rep
         out = dict(config=args.config, o=s.o, v=s.v, naux=s.naux, seed=s.seed, scale=s.scale, run=name,
-                   precision=prec, polish_residual=pol, polish_precision=pprec, tol=args.tol,
+                   precision=prec, other_precision=oprec, polish_residual=pol, polish_precision=pprec, tol=args.tol,
                    tol_energy=args.tol_energy,
                    converged=rep.converged, iterations=rep.iterations, polish_iteration=rep.polish_iteration,
                    e_corr=rep.e_corr, delta_e_vs_fp64=rep.e_corr - ref.e_corr,

@@ -215,8 +215,10 @@ struct Ctx {
   }
   Tensor t4(const double* p, long a, long b, long c, long d) const { return Tensor(p, {a, b, c, d}); }
 
+  // arithmetic of the large non-ladder contractions (RI_PREC_FP64 or RI_PREC_FP32)
+  int other_prec = RI_PREC_FP64;
   int es(const char* spec, double al, const Tensor& A, const Tensor& Bt, double be, const Tensor& C) {
-    return einsum(spec, al, A, Bt, be, C, arena, s);
+    return einsum(spec, al, A, Bt, be, C, arena, s, other_prec);
   }
 
   // (kc|ld) as gov[k][c][l][d]
@@ -426,6 +428,7 @@ void ri_ccsd_default_opts(ri_ccsd_opts* op) {
   op->check_fp64 = 0;
   op->mlp = nullptr;
   op->polish_precision = RI_PREC_FP64;
+  op->other_precision = RI_PREC_FP64;
 }
 
 int ri_mp2_guess(const ri_system* sys, double* t1, double* t2, double* e_mp2, void* stream) {
@@ -495,14 +498,21 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
   else ri_ccsd_default_opts(&op);
   if (op.max_iter < 0 || op.diis_size > 16 || op.guess < RI_GUESS_MP2 || op.guess > RI_GUESS_MLP ||
       !(op.polish_residual >= 0.0) || (op.guess == RI_GUESS_MLP && !op.mlp) ||
-      (op.polish_precision != RI_PREC_FP64 && op.polish_precision != RI_PREC_FP32)) {
+      (op.polish_precision != RI_PREC_FP64 && op.polish_precision != RI_PREC_FP32) ||
+      (op.other_precision != RI_PREC_FP64 && op.other_precision != RI_PREC_FP32)) {
     set_error("ri_ccsd_iterate: invalid options (max_iter %d, diis_size %d, guess %d, polish %g, mlp %p)",
               op.max_iter, op.diis_size, op.guess, op.polish_residual, static_cast<void*>(op.mlp));
     return RI_E_ARG;
   }
-  const bool mixed = op.ppl_precision != RI_PREC_FP64;
-  const bool polish = mixed && op.polish_residual > 0.0 && op.polish_precision != op.ppl_precision;
-  const int final_prec = polish ? op.polish_precision : op.ppl_precision;
+  // reduced precision in the ladder or the other large contractions; the polish
+  // moves the ladder to polish_precision and, for an FP64 polish, the others to FP64
+  const bool mixed = op.ppl_precision != RI_PREC_FP64 || op.other_precision != RI_PREC_FP64;
+  const int final_prec_p = op.polish_precision;
+  const int final_other_p = op.polish_precision == RI_PREC_FP64 ? RI_PREC_FP64 : op.other_precision;
+  const bool polish = mixed && op.polish_residual > 0.0 &&
+                      (final_prec_p != op.ppl_precision || final_other_p != op.other_precision);
+  const int final_prec = polish ? final_prec_p : op.ppl_precision;
+  const int final_other = polish ? final_other_p : op.other_precision;
   const int slots = op.diis_size >= 2 ? op.diis_size : 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
   cc::Ctx c(sys, s);
@@ -521,6 +531,7 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
     cc::symmetrize_kernel<<<cc::nblk(c.noovv), 256, 0, s>>>(tv2, c.o, c.v);
     RI_TRY(check_launch("symmetrize_kernel"));
   }
+  c.other_prec = op.other_precision;
   double hostv[64];
   RI_TRY(c.energy(tv1, tv2, c.scal));
   RI_TRY(c.read_scalars(hostv, 1));
@@ -553,7 +564,7 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
       status = RI_E_NUMERIC;
       break;
     }
-    const bool on_final = prec == final_prec;
+    const bool on_final = prec == final_prec && c.other_prec == final_other;
     if (it > 0 && rinf <= op.tol_residual && std::fabs(e - e_prev) <= op.tol_energy && on_final) {
       conv = true;
       break;
@@ -562,6 +573,7 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
     // uses this mixed residual)
     if (polish && !on_final && rinf <= op.polish_residual) {
       prec = final_prec;
+      c.other_prec = final_other;
       polish_it = it + 1;
     }
     // Jacobi step into the next history slot
@@ -623,10 +635,11 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
   // max |Omega| of the returned amplitudes with the FP64 ladder
   double rinf64 = NAN;
   if (status == RI_OK) {
-    if (conv && prec == RI_PREC_FP64) {
+    if (conv && prec == RI_PREC_FP64 && c.other_prec == RI_PREC_FP64) {
       rinf64 = rinf;
     } else if (mixed && op.check_fp64) {
       float ms = 0.f;
+      c.other_prec = RI_PREC_FP64;
       RI_TRY(c.residual(tv1, tv2, c.om, c.om + nov, RI_PREC_FP64, &ms));
       RI_TRY(max_abs(c.om, nt, c.part, c.scal, s));
       RI_TRY(c.read_scalars(hostv, 1));

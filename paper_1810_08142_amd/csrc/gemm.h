@@ -28,8 +28,11 @@ struct GemmDesc {
 // Doubles of scratch the split-k form of a contraction wants (0: not split).
 size_t scratch_doubles(const GemmDesc& g, int batch);
 // Launches the contraction; it is split over k when `scratch` holds at least
-// scratch_doubles(g, batch) doubles, else it runs in one pass.
-int run(const GemmDesc& g, int batch, double* scratch, size_t scratch_len, hipStream_t s);
+// scratch_doubles(g, batch) doubles, else it runs in one pass.  prec RI_PREC_FP32 lets
+// the large-tile kernel round its operands to FP32 and use the FP32 MFMA (the
+// smaller kernels always run in FP64).
+int run(const GemmDesc& g, int batch, double* scratch, size_t scratch_len, hipStream_t s,
+        int prec = RI_PREC_FP64);
 
 }  // namespace gemm
 
@@ -66,7 +69,7 @@ struct GemmArena {
 // dimension).  Letters are merged into the contraction's index levels when their
 // strides allow; at most 2 output-row, 2 output-column and 3 summed levels remain.
 int einsum(const char* spec, double alpha, const Tensor& A, const Tensor& B, double beta, const Tensor& out,
-           GemmArena& arena, hipStream_t s);
+           GemmArena& arena, hipStream_t s, int prec = RI_PREC_FP64);
 
 // out = alpha * permute(in) + beta * out, with spec like "kiac->aikc" (in -> out letters).
 int axpby_perm(const char* spec, double alpha, const Tensor& in, double beta, const Tensor& out, hipStream_t s);

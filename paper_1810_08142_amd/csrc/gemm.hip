@@ -17,6 +17,29 @@ namespace ri {
 namespace gemm {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Arithmetic of the large-tile kernel: FP64 operands on the FP64 MFMA, or operands
+// rounded to FP32 on the FP32 MFMA (FP32 accumulation).  Both are 16x16x4 tiles with
+// the same operand layout; element r of lane l holds D[drow(r, l)][l % 16].
+template <class T>
+struct GMma;
+template <>
+struct GMma<double> {
+  typedef double4_t acc_t;
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int drow(int r, int lane) { return 4 * r + (lane >> 4); }
+  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+};
+template <>
+struct GMma<float> {
+  typedef f32x4_t acc_t;
+  __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int drow(int r, int lane) { return 4 * (lane >> 4) + r; }
+  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+};
 
 constexpr int BM = 64, BN = 64, KC = 16;
 
@@ -167,10 +190,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmDesc g, int a_kfast, 
 // a 2 x 2 arrangement, each wave 64 x 64 (4 x 4 MFMA tiles).  grid (ceil(N/128),
 // ceil(M/128), batch), no split.
 constexpr int BL = 128;
-template <int a_kfast, int b_kfast>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_f64_large(GemmDesc g) {
-  __shared__ double sA[2][KC][BL + 2];
-  __shared__ double sB[2][KC][BL + 2];
+template <class T, int a_kfast, int b_kfast>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_large(GemmDesc g) {
+  typedef GMma<T> MF;
+  __shared__ T sA[2][KC][BL + 2];
+  __shared__ T sB[2][KC][BL + 2];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const long bm = static_cast<long>(blockIdx.y) * BL, bn = static_cast<long>(blockIdx.x) * BL;
   const long zb = blockIdx.z;
@@ -195,11 +219,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   long k2 = 0, k3 = 0, ka = 0, kb = 0;
   const long nchunks = g.K / KC;
 
-  double4_t acc[4][4];
+  typename MF::acc_t acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = MF::zero();
   const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
   const int l16 = lane & 15, kq = lane >> 4;
   double ra[8], rb[8];
@@ -210,8 +234,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    sA[0][A_K(r)][A_ROW(r)] = ra[r];
-    sB[0][B_K(r)][B_ROW(r)] = rb[r];
+    sA[0][A_K(r)][A_ROW(r)] = static_cast<T>(ra[r]);
+    sB[0][B_K(r)][B_ROW(r)] = static_cast<T>(rb[r]);
   }
   __syncthreads();
   for (long ch = 0; ch < nchunks; ++ch) {
@@ -241,7 +265,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int s4 = 0; s4 < KC / 4; ++s4) {
       const int kk = 4 * s4 + kq;
-      double a[4], b[4];
+      T a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = sA[buf][kk][wm + 16 * i + l16];
 #pragma unroll
@@ -249,18 +273,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = MF::mma(a[i], b[j], acc[i][j]);
     }
     if (more) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        sA[buf ^ 1][A_K(r)][A_ROW(r)] = ra[r];
-        sB[buf ^ 1][B_K(r)][B_ROW(r)] = rb[r];
+        sA[buf ^ 1][A_K(r)][A_ROW(r)] = static_cast<T>(ra[r]);
+        sB[buf ^ 1][B_K(r)][B_ROW(r)] = static_cast<T>(rb[r]);
       }
     }
     __syncthreads();
   }
-  // D[4r + lane/16][lane%16] in element r
+  // element r of a lane: D[drow(r, lane)][lane % 16]
   double* C = g.c + zb * g.c_batch;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -271,10 +295,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const long cn = (n / g.N2) * g.cn1 + (n % g.N2) * g.cn2;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const long m = bm + wm + 16 * i + 4 * r + kq;
+        const long m = bm + wm + 16 * i + MF::drow(r, lane);
         if (m >= g.M) continue;
         double* p = C + (m / g.M2) * g.cm1 + (m % g.M2) * g.cm2 + cn;
-        const double val = g.alpha * acc[i][j][r];
+        const double val = g.alpha * static_cast<double>(acc[i][j][r]);
         *p = g.beta == 0.0 ? val : val + g.beta * *p;
       }
     }
@@ -309,7 +333,7 @@ size_t scratch_doubles(const GemmDesc& g, int batch) {
   return static_cast<size_t>(splits) * g.M * g.N;
 }
 
-int run(const GemmDesc& g, int batch, double* scratch, size_t scratch_len, hipStream_t s) {
+int run(const GemmDesc& g, int batch, double* scratch, size_t scratch_len, hipStream_t s, int prec) {
   if (g.M <= 0 || g.N <= 0 || batch <= 0) return RI_OK;
   if (g.K <= 0) {
     set_error("gemm: K must be positive");
@@ -327,11 +351,18 @@ int run(const GemmDesc& g, int batch, double* scratch, size_t scratch_len, hipSt
   if (g.K3 % KC == 0 && tiles_l >= min_tiles) {
     dim3 grid(static_cast<unsigned>((g.N + BL - 1) / BL), static_cast<unsigned>((g.M + BL - 1) / BL),
               static_cast<unsigned>(batch));
-    if (a_kfast && b_kfast) gemm_f64_large<1, 1><<<grid, 256, 0, s>>>(g);
-    else if (a_kfast) gemm_f64_large<1, 0><<<grid, 256, 0, s>>>(g);
-    else if (b_kfast) gemm_f64_large<0, 1><<<grid, 256, 0, s>>>(g);
-    else gemm_f64_large<0, 0><<<grid, 256, 0, s>>>(g);
-    return check_launch("gemm_f64_large");
+    if (prec == RI_PREC_FP32) {
+      if (a_kfast && b_kfast) gemm_large<float, 1, 1><<<grid, 256, 0, s>>>(g);
+      else if (a_kfast) gemm_large<float, 1, 0><<<grid, 256, 0, s>>>(g);
+      else if (b_kfast) gemm_large<float, 0, 1><<<grid, 256, 0, s>>>(g);
+      else gemm_large<float, 0, 0><<<grid, 256, 0, s>>>(g);
+    } else {
+      if (a_kfast && b_kfast) gemm_large<double, 1, 1><<<grid, 256, 0, s>>>(g);
+      else if (a_kfast) gemm_large<double, 1, 0><<<grid, 256, 0, s>>>(g);
+      else if (b_kfast) gemm_large<double, 0, 1><<<grid, 256, 0, s>>>(g);
+      else gemm_large<double, 0, 0><<<grid, 256, 0, s>>>(g);
+    }
+    return check_launch("gemm_large");
   }
   const size_t want = scratch_doubles(g, batch);
   int splits = 1;

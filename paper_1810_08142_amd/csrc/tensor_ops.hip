@@ -70,7 +70,7 @@ std::vector<Level> merge(const std::vector<Level>& in) {
 }  // namespace
 
 int einsum(const char* spec, double alpha, const Tensor& A, const Tensor& B, double beta, const Tensor& C,
-           GemmArena& arena, hipStream_t s) {
+           GemmArena& arena, hipStream_t s, int prec) {
   Spec sp;
   if (!parse(spec, sp) || sp.a.size() != A.dims.size() || sp.b.size() != B.dims.size() ||
       sp.c.size() != C.dims.size()) {
@@ -172,7 +172,7 @@ int einsum(const char* spec, double alpha, const Tensor& A, const Tensor& B, dou
   const size_t need = gemm::scratch_doubles(g, nb);
   if (need) RI_TRY(arena.reserve(need));
   ProfScope ps(s, spec, 2.0 * static_cast<double>(g.M) * g.N * g.K * nb);
-  return gemm::run(g, nb, arena.p, arena.cap, s);
+  return gemm::run(g, nb, arena.p, arena.cap, s, prec);
 }
 
 // ------------------------------------------------------------------ permuted axpby

@@ -186,3 +186,22 @@ def test_mixed_ladder_with_fp32_polish():
     # converged on an FP32-ladder residual; the FP64 residual of the result is evaluated
     assert np.isfinite(rp.residual_inf_fp64) and rp.residual_inf_fp64 <= 1e-7
     assert abs(rp.e_corr - r64.e_corr) <= 1e-8
+
+
+def test_fp32_other_contractions_and_fp64_polish(monkeypatch):
+    """The large non-ladder contractions in FP32 (forced onto the large-tile kernel at
+    this size) stay within 1e-7 Eh of FP64; an FP64 polish returns to the FP64
+    fixed point."""
+    monkeypatch.setenv("RI_GEMM_LARGE_MIN_TILES", "1")
+    o, v, naux = 3, 32, 40
+    s = draw_system(o, v, naux, seed=880)
+    B, eps = dev(s.B), dev(s.eps)
+    _, _, r64 = _cc().solve(B, eps, o, tol=1e-10, tol_energy=1e-10)
+    _, _, r32 = _cc().solve(B, eps, o, other_precision="fp32", tol=1e-8, tol_energy=1e-9, check_fp64=True)
+    print("fp64", r64, "fp32 others", r32, flush=True)
+    assert r32.converged and abs(r32.e_corr - r64.e_corr) <= 1e-7
+    assert np.isfinite(r32.residual_inf_fp64) and r32.residual_inf_fp64 <= 1e-6
+    _, _, rp = _cc().solve(B, eps, o, other_precision="fp32", polish_residual=1e-6, tol=1e-10, tol_energy=1e-10)
+    assert rp.converged and rp.polish_iteration > 0
+    assert rp.residual_inf_fp64 == rp.residual_inf <= 1e-10
+    assert abs(rp.e_corr - r64.e_corr) <= 1e-10
