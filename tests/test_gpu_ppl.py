@@ -218,3 +218,18 @@ def test_shards_add_up_to_the_whole_call(precision, monkeypatch):
     from paper_1810_08142_amd import _lib
     with pytest.raises(_lib.RIError):
         _ppl().ppl(B, T, full, precision=precision, shard=(3, 3))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_power_of_two_scaling_is_bitwise(precision):
+    """R(2^k B, 2^m tau) = 2^(2k+m) R(B, tau) exactly: power-of-two scaling commutes
+    with every rounding step, the bf16 hi/lo split included (no under/overflow here)."""
+    import torch
+    o, v, naux = 3, 37, 29
+    s = draw_system(o, v, naux, seed=961)
+    tau = draw_pair_symmetric(o, v, 962)
+    R1 = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    R2 = torch.zeros_like(R1)
+    _ppl().ppl(dev(s.B_vv), dev(tau), R1, precision=precision)
+    _ppl().ppl(dev(s.B_vv * 4.0), dev(tau * 0.5), R2, precision=precision)  # 2^(2*2 - 1) = 8
+    assert bool((R2 == 8.0 * R1).all())

@@ -122,3 +122,62 @@ def test_ccsd_with_mixed_ladder_energy_within_microhartree(precision):
     print("E fp64", r64.e_corr, f"E {precision}", rmx.e_corr, "diff", rmx.e_corr - r64.e_corr, flush=True)
     assert r64.converged and rmx.converged
     assert abs(rmx.e_corr - r64.e_corr) <= 1e-6
+
+
+def _bf16_rne(x32):
+    """Round float32 values to bfloat16 (nearest even), returned as float64."""
+    u = np.asarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _split(x):
+    """x = hi + lo: hi = bf16(fp32(x)), lo = bf16(fp32(x - hi))."""
+    hi = _bf16_rne(np.asarray(x, dtype=np.float64).astype(np.float32))
+    lo = _bf16_rne((np.asarray(x, dtype=np.float64) - hi).astype(np.float32))
+    return hi, lo
+
+
+def _split_ladder_emulated(B_vv, tau):
+    """The split-bf16 ladder's arithmetic on the host: operands split once, products
+    hi*lo + lo*hi + hi*hi (exact in FP64), integrals rounded to FP32 and split again for
+    the contraction, S and A rounded to FP32.  Only the FP32 accumulation order of the
+    device differs."""
+    o, v = tau.shape[0], tau.shape[2]
+    Bh, Bl = _split(B_vv)
+    prod = lambda x, y: (np.einsum("Qac,Qbd->abcd", x[0], y[1]) + np.einsum("Qac,Qbd->abcd", x[1], y[0])
+                         + np.einsum("Qac,Qbd->abcd", x[0], y[0]))
+    v1 = prod((Bh, Bl), (Bh, Bl)).astype(np.float32)          # (ac|bd)[a, b, c, d]
+    v2 = v1.transpose(0, 1, 3, 2)                             # (ad|bc)
+    Wp = _split((v1 + v2).astype(np.float32))
+    Wm = _split((v1 - v2).astype(np.float32))
+    tp = 0.5 * (tau + tau.transpose(0, 1, 3, 2))  # (tau^{cd} + tau^{dc}) / 2 (tau is pair-symmetric)
+    tm = 0.5 * (tau - tau.transpose(0, 1, 3, 2))
+    iu = np.triu_indices(v)
+    sig = np.where(iu[0] == iu[1], 0.5, 1.0)
+    Tp = _split(tp[:, :, iu[0], iu[1]] * sig)
+    iu1 = np.triu_indices(v, 1)
+    Tm = _split(tm[:, :, iu1[0], iu1[1]])
+    c3 = lambda W, T, idx: (np.einsum("abk,ijk->ijab", W[0][:, :, idx[0], idx[1]], T[1])
+                            + np.einsum("abk,ijk->ijab", W[1][:, :, idx[0], idx[1]], T[0])
+                            + np.einsum("abk,ijk->ijab", W[0][:, :, idx[0], idx[1]], T[0]))
+    S = c3(Wp, Tp, iu).astype(np.float32).astype(np.float64)
+    A = c3(Wm, Tm, iu1).astype(np.float32).astype(np.float64)
+    return S + A
+
+
+def test_split_emulation_reproduces_the_device_result():
+    o, v, naux = 2, 20, 40
+    s = draw_system(o, v, naux, seed=971)
+    tau = draw_pair_symmetric(o, v, 972)
+    got = _ladder(s.B_vv, tau, "bf16x3")
+    emu = _split_ladder_emulated(s.B_vv, tau)
+    ref = native.ppl(s.B_vv, tau)
+    scale = native.ppl(np.abs(s.B_vv), np.abs(tau))
+    d_emu = np.abs(got - emu)
+    d_ref = np.abs(got - ref)
+    print("device vs emulation", float(d_emu.max()), "device vs FP64", float(d_ref.max()), flush=True)
+    # the device differs from the emulation only by FP32 accumulation order ...
+    assert bool(np.all(d_emu <= 1e-6 * scale))
+    # ... which is far below the split error it shares with the emulation
+    assert float(d_emu.max()) < 0.1 * float(d_ref.max())

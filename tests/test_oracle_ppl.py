@@ -154,3 +154,31 @@ def test_rejects_bad_arguments():
     tau = np.zeros((1, 1, 3, 3))
     with pytest.raises(RuntimeError):
         native.ppl_pairs(B, tau, [(0, 3)])
+
+
+def test_symmetric_antisymmetric_split_equals_full_sum():
+    """Scuseria's split used by the GPU path (Sec. II.C): with tau+- = (tau^{cd} +-
+    tau^{dc}) / 2 over c <= d (weight 1/2 at c = d) and c < d, V+- = (ac|bd) +- (ad|bc),
+    S = sum V+ tau+ and A = sum V- tau-, the ladder is S + A for (ab, ij) and S - A for
+    (ba, ij).  Written here from those definitions and compared with the plain sum."""
+    o, v, naux = 3, 7, 5
+    s = draw_system(o, v, naux, seed=57)
+    tau = draw_pair_symmetric(o, v, 58)
+    B = s.B_vv
+    eri = np.einsum("Qac,Qbd->abcd", B, B)  # (ac|bd) as eri[a, b, c, d]
+    R = np.zeros((o, o, v, v))
+    for a in range(v):
+        for b in range(v):
+            for i in range(o):
+                for j in range(o):
+                    S = A = 0.0
+                    for c in range(v):
+                        for d in range(c, v):
+                            vp = eri[a, b, c, d] + eri[a, b, d, c]
+                            tp = 0.5 * (tau[i, j, c, d] + tau[i, j, d, c])
+                            S += (0.5 if c == d else 1.0) * vp * tp
+                            if c < d:
+                                A += (eri[a, b, c, d] - eri[a, b, d, c]) * 0.5 * (tau[i, j, c, d] - tau[i, j, d, c])
+                    R[i, j, a, b] = S + A
+    ref = native.ppl(B, tau)
+    assert np.abs(R - ref).max() <= 1e-13 * np.abs(ref).max()
