@@ -129,7 +129,8 @@ typedef struct ri_system {
 
 #define RI_GUESS_MP2 0  /* t1 = 0, t2 = (ia|jb) / D (iteration 0) */
 #define RI_GUESS_USER 1 /* start from the t1, t2 passed in */
-#define RI_GUESS_MLP 2  /* the MP2 guess corrected by the network opts->mlp (ri_mlp_guess) */
+#define RI_GUESS_MLP 2  /* the MP2 guess corrected by the network opts->mlp (ri_mlp_guess);
+                           falls back to RI_GUESS_MP2 if that fails or is non-finite */
 
 typedef struct ri_mlp ri_mlp; /* learned starting guess, declared below */
 
@@ -175,6 +176,8 @@ typedef struct ri_ccsd_report {
   int polish_iteration; /* first iteration whose residual used the polish ladder after a
                            mixed start (-1: none) */
   double seconds_guess; /* wall time until the guess and its energy were ready */
+  int guess_used;       /* RI_GUESS_* actually used: RI_GUESS_MLP falls back to RI_GUESS_MP2
+                           when the network fails or gives non-finite amplitudes */
 } ri_ccsd_report;
 
 /* Fills the defaults listed above. */

@@ -38,7 +38,7 @@ class RICcsdReport(_c.Structure):
     _fields_ = [("e_corr", _c.c_double), ("e_mp2", _c.c_double), ("residual_inf", _c.c_double),
                 ("iterations", _c.c_int), ("converged", _c.c_int), ("seconds_total", _c.c_double),
                 ("seconds_ppl", _c.c_double), ("residual_rms", _c.c_double), ("residual_inf_fp64", _c.c_double),
-                ("polish_iteration", _c.c_int), ("seconds_guess", _c.c_double)]
+                ("polish_iteration", _c.c_int), ("seconds_guess", _c.c_double), ("guess_used", _c.c_int)]
 
 
 _sysp = _c.POINTER(RISystem)

@@ -72,6 +72,7 @@ class Report:
     residual_inf_fp64: float = float("nan")
     polish_iteration: int = -1
     seconds_guess: float = float("nan")
+    guess_used: int = 0  # 0 MP2, 1 user amplitudes, 2 learned (falls back to 0)
 
 
 def solve(B, eps, o, t1=None, t2=None, max_iter=100, tol=1e-10, tol_energy=1e-10, diis_size=6,
@@ -117,5 +118,5 @@ def solve(B, eps, o, t1=None, t2=None, max_iter=100, tol=1e-10, tol_energy=1e-10
         _lib.check(rc, "ri_ccsd_iterate")
     r = Report(rep.e_corr, rep.e_mp2, rep.residual_inf, rep.iterations, bool(rep.converged), rep.seconds_total,
                rep.seconds_ppl, rc, rep.residual_rms, rep.residual_inf_fp64, rep.polish_iteration,
-               rep.seconds_guess)
+               rep.seconds_guess, rep.guess_used)
     return t1, t2, r

@@ -521,10 +521,11 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
   const long nov = c.nov, nt = c.nt;
   double* tv1 = c.tvec;
   double* tv2 = c.tvec + nov;
+  int mlp_rc = RI_OK;
   if (op.guess == RI_GUESS_MP2) {
     RI_TRY(c.mp2(tv1, tv2));
   } else if (op.guess == RI_GUESS_MLP) {
-    RI_TRY(ri_mlp_guess(op.mlp, sys, tv1, tv2, stream));
+    mlp_rc = ri_mlp_guess(op.mlp, sys, tv1, tv2, stream);
   } else {
     RI_HIP(hipMemcpyAsync(tv1, t1, sizeof(double) * nov, hipMemcpyDeviceToDevice, s));
     RI_HIP(hipMemcpyAsync(tv2, t2, sizeof(double) * c.noovv, hipMemcpyDeviceToDevice, s));
@@ -533,10 +534,25 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
   }
   c.other_prec = op.other_precision;
   double hostv[64];
-  RI_TRY(c.energy(tv1, tv2, c.scal));
-  RI_TRY(c.read_scalars(hostv, 1));
-  double e = hostv[0];
-  const double e_mp2 = op.guess == RI_GUESS_MP2 ? e : NAN;
+  double e = NAN;
+  if (mlp_rc == RI_OK) {
+    RI_TRY(c.energy(tv1, tv2, c.scal));
+    RI_TRY(c.read_scalars(hostv, 1));
+    e = hostv[0];
+  }
+  // the MP2 guess is the learned guess's fallback: used when the network fails or
+  // gives non-finite amplitudes (their energy is then non-finite)
+  int guess_used = op.guess;
+  if (op.guess == RI_GUESS_MLP && (mlp_rc != RI_OK || !std::isfinite(e))) {
+    if (op.verbose) fprintf(stderr, "[ccsd] learned guess unusable (%s); starting from MP2\n", ri_status_str(mlp_rc));
+    clear_error();
+    RI_TRY(c.mp2(tv1, tv2));
+    RI_TRY(c.energy(tv1, tv2, c.scal));
+    RI_TRY(c.read_scalars(hostv, 1));
+    e = hostv[0];
+    guess_used = RI_GUESS_MP2;
+  }
+  const double e_mp2 = guess_used == RI_GUESS_MP2 ? e : NAN;
   const double sec_guess = std::chrono::duration<double>(clk::now() - t_start).count();
   double e_prev = NAN, rinf = INFINITY, rrms = INFINITY;
   int prec = op.ppl_precision, polish_it = -1;
@@ -654,6 +670,7 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
     rep->residual_inf_fp64 = rinf64;
     rep->polish_iteration = polish_it;
     rep->seconds_guess = sec_guess;
+    rep->guess_used = guess_used;
     rep->e_corr = e;
     rep->e_mp2 = e_mp2;
     rep->residual_inf = rinf;

@@ -106,7 +106,8 @@ def train(X, Y, hidden=256, layers=2, epochs=30, batch=4096, lr=5e-4, seed=0, ho
     return net, hist
 
 
-def evaluate(net, config="c5", scale="naux", precision="fp64", tol=1e-8, log=None):
+def evaluate(net, config="c5", scale="naux", precision="fp64", tol=1e-8, log=None, polish_residual=0.0,
+             polish_precision="fp64"):
     """Iterations and wall time to convergence from the MP2 and from the learned guess
     (the latter through the solver's learned-guess option, so its time includes the
     features and the network), plus the error of both guesses against the converged
@@ -120,9 +121,12 @@ def evaluate(net, config="c5", scale="naux", precision="fp64", tol=1e-8, log=Non
     B = torch.from_numpy(s.B).to("cuda")
     eps = torch.from_numpy(s.eps).to("cuda")
     torch.cuda.synchronize()
-    out = dict(config=config, o=s.o, v=s.v, naux=s.naux, seed=s.seed, scale=s.scale, precision=precision, tol=tol)
-    _, t2a, ra = ccsd.solve(B, eps, s.o, tol=tol, tol_energy=tol * 0.1, ppl_precision=precision)
-    _, t2b, rb = ccsd.solve(B, eps, s.o, tol=tol, tol_energy=tol * 0.1, ppl_precision=precision, mlp=net)
+    out = dict(config=config, o=s.o, v=s.v, naux=s.naux, seed=s.seed, scale=s.scale, precision=precision, tol=tol,
+               polish_residual=polish_residual, polish_precision=polish_precision)
+    kw = dict(tol=tol, tol_energy=tol * 0.1, ppl_precision=precision, polish_residual=polish_residual,
+              polish_precision=polish_precision)
+    _, t2a, ra = ccsd.solve(B, eps, s.o, **kw)
+    _, t2b, rb = ccsd.solve(B, eps, s.o, mlp=net, **kw)
     # guess errors (outside the timed solves)
     _, t2g = net.guess(B, eps, s.o)
     t2m, _ = ccsd.mp2_guess(B, eps, s.o)
@@ -133,7 +137,7 @@ def evaluate(net, config="c5", scale="naux", precision="fp64", tol=1e-8, log=Non
     out["mp2_guess"] = dict(iterations=ra.iterations, seconds=ra.seconds_total, seconds_guess=ra.seconds_guess,
                             e_corr=ra.e_corr, converged=ra.converged)
     out["learned_guess"] = dict(iterations=rb.iterations, seconds=rb.seconds_total, seconds_guess=rb.seconds_guess,
-                                e_corr=rb.e_corr, converged=rb.converged)
+                                e_corr=rb.e_corr, converged=rb.converged, guess_used=rb.guess_used)
     out["delta_e_corr"] = rb.e_corr - ra.e_corr
     out["max_abs_delta_t2"] = float((t2a - t2b).abs().max())
     out["speedup"] = ra.seconds_total / rb.seconds_total
@@ -157,6 +161,8 @@ def main(argv=None):
     e.add_argument("--model", required=True)
     e.add_argument("--config", default="c5")
     e.add_argument("--precision", default="fp64")
+    e.add_argument("--polish", type=float, default=0.0)
+    e.add_argument("--polish-precision", default="fp64")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -180,7 +186,8 @@ def main(argv=None):
         print(json.dumps(res), flush=True)
     else:
         net = mlp.Net.load(args.model)
-        print(json.dumps(evaluate(net, args.config, precision=args.precision, log=log)), flush=True)
+        print(json.dumps(evaluate(net, args.config, precision=args.precision, log=log, polish_residual=args.polish,
+                                  polish_precision=args.polish_precision)), flush=True)
     return 0
 
 

@@ -205,3 +205,25 @@ def test_fp32_other_contractions_and_fp64_polish(monkeypatch):
     assert rp.converged and rp.polish_iteration > 0
     assert rp.residual_inf_fp64 == rp.residual_inf <= 1e-10
     assert abs(rp.e_corr - r64.e_corr) <= 1e-10
+
+
+def test_learned_guess_falls_back_to_mp2():
+    from paper_1810_08142_amd import mlp
+    o, v, naux = 3, 20, 40
+    s = draw_system(o, v, naux, seed=890)
+    B, eps = dev(s.B), dev(s.eps)
+    _, _, r0 = _cc().solve(B, eps, o, tol=1e-10, tol_energy=1e-11)
+    net = mlp.Net()
+    theta = mlp.init_params(8, 256, 2, seed=6)
+    theta[-1] = np.nan  # a broken network: every amplitude becomes NaN
+    net.set_params(theta)
+    net.set_scaling(np.zeros(8), np.ones(8), 1.0)
+    _, _, r = _cc().solve(B, eps, o, mlp=net, tol=1e-10, tol_energy=1e-11)
+    assert r.guess_used == 0 and r.converged
+    assert r.e_corr == r0.e_corr and r.iterations == r0.iterations
+    assert r0.guess_used == 0
+    good = mlp.Net()
+    good.set_params(mlp.init_params(8, 256, 2, seed=5))
+    good.set_scaling(np.zeros(8), np.ones(8), 1e-4)
+    _, _, r2 = _cc().solve(B, eps, o, mlp=good, tol=1e-10, tol_energy=1e-11)
+    assert r2.guess_used == 2 and r2.converged
