@@ -77,8 +77,8 @@ int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double
  * precisions round B_vv and the packed tau once to their operand type (FP32, or a
  * bf16 hi + lo pair), rebuild the integrals with FP32 accumulation, round them
  * again for the contraction and add the FP32 result into the FP64 R; the error of
- * an element is bounded by 2e-4 times the ladder of |B_vv| and |tau| (and is
- * typically 1e-6 of max |R| for bf16 hi + lo, less for FP32). */
+ * an element is bounded by 2e-4 times the ladder of |B_vv| and |tau| (and is a few
+ * 1e-6 of max |R| for bf16 hi + lo, less for FP32). */
 int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
               int precision, void* ws, size_t ws_bytes, void* stream);
 
@@ -169,9 +169,9 @@ typedef struct ri_ccsd_report {
   double seconds_total; /* wall time of the call, guess included, check_fp64 excluded */
   double seconds_ppl;   /* GPU time of the ladder term */
   double residual_rms;  /* root mean square of Omega at the last residual evaluation */
-  /* max |Omega| of the returned amplitudes with the FP64 ladder: equals
-   * residual_inf when the last residual used it (converged FP64 or polished runs),
-   * NaN when not evaluated */
+  /* max |Omega| of the returned amplitudes evaluated in FP64 throughout: equals
+   * residual_inf when a converged run's last residual was FP64 throughout (FP64 runs,
+   * FP64-polished runs), else the check_fp64 evaluation, else NaN */
   double residual_inf_fp64;
   int polish_iteration; /* first iteration whose residual used the polish ladder after a
                            mixed start (-1: none) */
@@ -193,8 +193,8 @@ int ri_ccsd_energy(const ri_system* sys, const double* t1, const double* t2, dou
 
 /* CCSD residuals for the given amplitudes: omega1 [o][v], omega2 [o][o][v][v]
  * (projections of eqs. ccsd-2/-3 in the biorthogonal basis; at t = 0 omega2 is
- * (ia|jb) and omega1 is 0).  The ladder term uses ppl_precision.  Outputs must
- * not overlap the amplitudes. */
+ * (ia|jb) and omega1 is 0).  The ladder term uses ppl_precision, everything else
+ * FP64.  Outputs must not overlap the amplitudes. */
 int ri_ccsd_residual(const ri_system* sys, const double* t1, const double* t2, double* omega1, double* omega2,
                      int ppl_precision, void* stream);
 
