@@ -34,7 +34,8 @@ typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));  // one 16-byt
 
 constexpr int QC = 32;  // RI functions per build step (= MFMA K)
 constexpr int KB = 32;  // cd slots per contraction step (= MFMA K)
-constexpr int CBM = 128;  // contraction tile rows
+constexpr int CBM = 256;  // contraction tile rows
+constexpr int CNT = 2 * CBM;  // contraction threads: CBM / 32 waves of 32 rows each
 
 __host__ __device__ inline uint16_t bf16_bits(float f) {
   // round to nearest even (inputs are finite)
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict
 // be split over grid.z: split z sums k in [z*kz, min(K, (z+1)*kz)) into C + z*zs.
 // grid (ncol/(16*NTW), rows/128, splits), block 256
 template <int NTW>
-__global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
+__global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
                                                        const uint16_t* __restrict__ Th, const uint16_t* __restrict__ Tl,
                                                        long K, int ncol, float* __restrict__ C, long kz, long zs) {
   constexpr int BN = 16 * NTW;
@@ -306,14 +307,14 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
   const long k_len = (K < k_lo + kz ? K : k_lo + kz) - k_lo;
   C += blockIdx.z * zs;
 
-  // staging: A 1024 runs (4 per thread), B 8*BN runs (ceil(BN/32) per thread)
-  constexpr int BPER = (BRUNS + 255) / 256;
+  // staging: A 8*CBM runs (4 per thread), B 8*BN runs (BPER per thread, the last may idle)
+  constexpr int BPER = (BRUNS + CNT - 1) / CNT;
   size_t aoff[4];
   int alo[4];
   const uint16_t* asrc[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int id = t + 256 * r;
+    const int id = t + CNT * r;
     const int row = id >> 3, hl = (id >> 2) & 1, run = id & 3;
     asrc[r] = hl ? Wl : Wh;
     aoff[r] = static_cast<size_t>(m0 + row) * K + k_lo + run * 8;
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(256) void contract_bf16x3(const uint16_t* __restric
   const uint16_t* bsrc[BPER];
 #pragma unroll
   for (int r = 0; r < BPER; ++r) {
-    const int id = t + 256 * r;
+    const int id = t + CNT * r;
     const int row = (id >> 3) < BN ? (id >> 3) : 0, hl = (id >> 2) & 1, run = id & 3;
     bsrc[r] = hl ? Tl : Th;
     boff[r] = static_cast<size_t>(n0 + row) * K + k_lo + run * 8;
@@ -477,7 +478,7 @@ static bool make_mplan(int o, int v, int naux, MPlan& p) {
 template <int NTW>
 static void launch_c(const uint16_t* Wh, const uint16_t* Wl, const uint16_t* Th, const uint16_t* Tl, long K,
                      long rows, int ncol, float* C, int splits, long kz, hipStream_t s) {
-  contract_bf16x3<NTW><<<dim3(ncol / (16 * NTW), rows / CBM, splits), 256, 0, s>>>(Wh, Wl, Th, Tl, K, ncol, C, kz,
+  contract_bf16x3<NTW><<<dim3(ncol / (16 * NTW), rows / CBM, splits), CNT, 0, s>>>(Wh, Wl, Th, Tl, K, ncol, C, kz,
                                                                                    rows * ncol);
 }
 
