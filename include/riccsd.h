@@ -239,6 +239,37 @@ int ri_mlp_gradient(ri_mlp* net, const float* X, const float* Y, long n, float* 
  * before the step when not NULL (synchronises stream). */
 int ri_mlp_train_step(ri_mlp* net, const float* X, const float* Y, long n, float lr, float* loss_host,
                       void* stream);
+/* Seeded starting parameters, written on `stream`: weight number i of the flat vector
+ * (layer fan-in f) is N(0, 1)/sqrt(f), the normal drawn by the Box-Muller transform
+ * from SplitMix64 outputs 2i and 2i+1 of `seed`; biases are zero; Adam restarts. */
+int ri_mlp_init(ri_mlp* net, unsigned long long seed, void* stream);
+/* Options of ri_mlp_train (ri_mlp_default_train_opts fills the defaults shown). */
+typedef struct ri_mlp_train_opts {
+  int epochs;               /* passes over the training set (30) */
+  long batch;               /* rows per Adam step (4096); an epoch takes max(1, n / batch)
+                               steps of min(batch, n) rows, the rest of the rows wait
+                               for a later shuffle */
+  float lr;                 /* peak learning rate (5e-4) */
+  float warmup;             /* fraction of all steps in the linear warm-up (0.05); after
+                               it the rate decays to zero on a half cosine */
+  unsigned long long seed;  /* shuffle seed (1) */
+  int shuffle;              /* 1: rows in a new order each epoch (Fisher-Yates driven by
+                               SplitMix64 of `seed`); 0: rows in the given order (1) */
+} ri_mlp_train_opts;
+void ri_mlp_default_train_opts(ri_mlp_train_opts* opts);
+/* Fit the network to device X [n][d_in] (standardised) and Y [n] by Adam steps
+ * (ri_mlp_train_step's update), the whole loop in the library: shuffle, batches,
+ * learning-rate schedule (step t of T with W warm-up steps, W = max(1, floor(T warmup)):
+ * lr min(1, (t+1)/W) (1 + cos(pi t / T)) / 2), and after each epoch the loss on the
+ * validation set (X_val [n_val][d_in], Y_val [n_val]; n_val = 0 for none).
+ * opts NULL takes the defaults.  train_loss / val_loss: host arrays of opts->epochs
+ * floats (or NULL) for each epoch's mean batch loss and validation loss; when either
+ * is given the call synchronises the stream and returns RI_E_NUMERIC if a loss is not
+ * finite.  n <= 2^28, batch <= 2^24.  Device workspace of n (d_in + 2) + n_val floats
+ * (about) is taken stream-ordered for the call; the host waits for each permutation copy
+ * before it reuses the host buffer, not for the training steps. */
+int ri_mlp_train(ri_mlp* net, const float* X, const float* Y, long n, const float* X_val, const float* Y_val,
+                 long n_val, const ri_mlp_train_opts* opts, float* train_loss, float* val_loss, void* stream);
 /* Raw (unstandardised) features of every amplitude, X [o][o][v][v][8] FP32, from the
  * MP2 t2 and the (ia|jb) integrals of sys: t2_ijab, t2_ijba, (ia|jb), (ib|ja),
  * e_i + e_j - e_a - e_b, (e_a - e_b)^2, (e_i - e_j)^2, sqrt((ia|ia)(jb|jb)). */

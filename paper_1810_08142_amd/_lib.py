@@ -41,6 +41,11 @@ class RICcsdReport(_c.Structure):
                 ("polish_iteration", _c.c_int), ("seconds_guess", _c.c_double), ("guess_used", _c.c_int)]
 
 
+class RIMlpTrainOpts(_c.Structure):
+    _fields_ = [("epochs", _c.c_int), ("batch", _c.c_long), ("lr", _c.c_float), ("warmup", _c.c_float),
+                ("seed", _c.c_ulonglong), ("shuffle", _c.c_int)]
+
+
 _sysp = _c.POINTER(RISystem)
 _dblp = _c.POINTER(_c.c_double)
 _fltp = _c.POINTER(_c.c_float)
@@ -74,6 +79,10 @@ _SIGS = [
     ("ri_mlp_forward", _c.c_int, [_c.c_void_p, _dp, _c.c_long, _dp, _dp]),
     ("ri_mlp_gradient", _c.c_int, [_c.c_void_p, _dp, _dp, _c.c_long, _dp, _fltp, _dp]),
     ("ri_mlp_train_step", _c.c_int, [_c.c_void_p, _dp, _dp, _c.c_long, _c.c_float, _fltp, _dp]),
+    ("ri_mlp_init", _c.c_int, [_c.c_void_p, _c.c_ulonglong, _dp]),
+    ("ri_mlp_default_train_opts", None, [_c.POINTER(RIMlpTrainOpts)]),
+    ("ri_mlp_train", _c.c_int, [_c.c_void_p, _dp, _dp, _c.c_long, _dp, _dp, _c.c_long, _c.POINTER(RIMlpTrainOpts),
+                                _fltp, _fltp, _dp]),
     ("ri_mlp_features", _c.c_int, [_sysp, _dp, _dp, _dp]),
     ("ri_mlp_guess", _c.c_int, [_c.c_void_p, _sysp, _dp, _dp, _dp]),
     ("ri_mlp_save", _c.c_int, [_c.c_void_p, _c.c_char_p]),

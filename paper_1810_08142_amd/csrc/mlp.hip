@@ -174,6 +174,7 @@ __global__ void tanh_back(const float* __restrict__ H, float* dH, long n) {
 
 constexpr int LB = 1024;
 // delta_out[r] = 2 (y - Y) / n and partials of sum (y - Y)^2
+// (delta may be NULL: loss only)
 __global__ __launch_bounds__(256) void mse_stage1(const float* __restrict__ y, const float* __restrict__ Y, long n,
                                                   float* delta, float* part) {
   __shared__ float sh[256];
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(256) void mse_stage1(const float* __restrict__ y, c
   float acc = 0.f;
   for (long i = lo + threadIdx.x; i < hi; i += 256) {
     const float r = y[i] - Y[i];
-    delta[i] = 2.f * r / static_cast<float>(n);
+    if (delta) delta[i] = 2.f * r / static_cast<float>(n);
     acc += r * r;
   }
   sh[threadIdx.x] = acc;
@@ -217,6 +218,54 @@ __global__ void adam_kernel(float* p, const float* __restrict__ g, float* m, flo
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output number c (c = 0, 1, ...)
+// of the stream seeded with `seed`.
+__host__ __device__ inline unsigned long long splitmix64(unsigned long long seed, unsigned long long c) {
+  unsigned long long z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Starting parameters of one layer (parameters [off, off + fin*fout + fout) of the
+// flat vector): weight number i gets N(0, 1)/sqrt(fin) by the Box-Muller transform of
+// the uniforms u1 = (x_{2i} >> 11 + 1) 2^-53 in (0, 1] and u2 = (x_{2i+1} >> 11) 2^-53,
+// x_c the SplitMix64 outputs of `seed` and i the flat parameter index; biases are zero.
+__global__ void init_layer(float* p, long off, int fin, int fout, unsigned long long seed) {
+  const long k = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long nw = static_cast<long>(fin) * fout;
+  if (k >= nw + fout) return;
+  const long i = off + k;
+  if (k >= nw) {
+    p[i] = 0.f;
+    return;
+  }
+  const double two53 = 1.0 / 9007199254740992.0;
+  const double u1 = static_cast<double>((splitmix64(seed, 2 * i) >> 11) + 1) * two53;
+  const double u2 = static_cast<double>(splitmix64(seed, 2 * i + 1) >> 11) * two53;
+  const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  p[i] = static_cast<float>(z / sqrt(static_cast<double>(fin)));
+}
+
+// rows r of (X, Y) in the order perm: Xs[r][:] = X[perm[r]][:], Ys[r] = Y[perm[r]]
+__global__ void gather_rows(const float* __restrict__ X, const float* __restrict__ Y, const int* __restrict__ perm,
+                            long n, int d, float* Xs, float* Ys) {
+  const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * (d + 1)) return;
+  const long r = t / (d + 1);
+  const int c = static_cast<int>(t - r * (d + 1));
+  const long src = perm[r];
+  if (c < d)
+    Xs[r * d + c] = X[src * d + c];
+  else
+    Ys[r] = Y[src];
+}
+
+// acc[0] += w * x[0]  (one thread; the epoch's mean batch loss, summed in step order)
+__global__ void add_scaled(float* acc, const float* __restrict__ x, float w) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) acc[0] += w * x[0];
 }
 
 // Features of amplitudes [row0, row0 + n) of the o*o*v*v flattened (i, j, a, b) set:
@@ -450,6 +499,36 @@ int gradient(ri_mlp* net, const float* X, const float* Y, long n, float* grad, h
   return RI_OK;
 }
 
+// One Adam step on net->grad with learning rate lr (beta1 0.9, beta2 0.999, eps 1e-8).
+int adam_step(ri_mlp* net, float lr, hipStream_t s) {
+  net->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, static_cast<float>(net->step)), c2 = 1.f - powf(b2, static_cast<float>(net->step));
+  adam_kernel<<<nblk(net->nparams), 256, 0, s>>>(net->params, net->grad, net->m, net->v, net->nparams, lr, b1, b2,
+                                                 1e-8f, c1, c2);
+  return check_launch("adam_kernel");
+}
+
+// Learning rate of step `it` of `total`: linear warm-up over `warm` steps, then
+// cosine decay to zero (evaluated in double, rounded once to float).
+inline float schedule(float lr, long it, long warm, long total) {
+  const double ramp = std::min(1.0, static_cast<double>(it + 1) / static_cast<double>(warm));
+  const double cosine = 1.0 + cos(3.141592653589793 * static_cast<double>(it) / static_cast<double>(total));
+  return static_cast<float>(static_cast<double>(lr) * ramp * 0.5 * cosine);
+}
+
+// Fisher-Yates shuffle of the identity permutation of n rows: for i = n-1 down to 1,
+// swap entries i and j = floor(x (i+1) / 2^64), x the next output of the SplitMix64
+// stream (counter *ctr, advanced by n-1).
+void shuffle(std::vector<int>& perm, long n, unsigned long long seed, unsigned long long* ctr) {
+  for (long r = 0; r < n; ++r) perm[r] = static_cast<int>(r);
+  for (long i = n - 1; i >= 1; --i) {
+    const unsigned long long x = splitmix64(seed, (*ctr)++);
+    const long j = static_cast<long>((static_cast<unsigned __int128>(x) * static_cast<unsigned long long>(i + 1)) >> 64);
+    std::swap(perm[i], perm[j]);
+  }
+}
+
 int check_net(const ri_mlp* net, const char* where) {
   if (!net || !net->params) {
     set_error("%s: null network", where);
@@ -611,15 +690,152 @@ int ri_mlp_train_step(ri_mlp* net, const float* X, const float* Y, long n, float
   hipStream_t s = static_cast<hipStream_t>(stream);
   RI_TRY(mlp::reserve(net, n, s));
   RI_TRY(mlp::gradient(net, X, Y, n, net->grad, s));
-  net->step += 1;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = 1.f - powf(b1, static_cast<float>(net->step)), c2 = 1.f - powf(b2, static_cast<float>(net->step));
-  mlp::adam_kernel<<<mlp::nblk(net->nparams), 256, 0, s>>>(net->params, net->grad, net->m, net->v, net->nparams, lr,
-                                                            b1, b2, 1e-8f, c1, c2);
-  RI_TRY(check_launch("adam_kernel"));
+  RI_TRY(mlp::adam_step(net, lr, s));
   if (loss_host) {
     RI_HIP(hipMemcpyAsync(loss_host, mlp::carve(net).loss, sizeof(float), hipMemcpyDeviceToHost, s));
     RI_HIP(hipStreamSynchronize(s));
+  }
+  return RI_OK;
+}
+
+int ri_mlp_init(ri_mlp* net, unsigned long long seed, void* stream) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_init"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  long off = 0;
+  for (int l = 0; l <= net->layers; ++l) {
+    float *W, *b;
+    int fi, fo;
+    mlp::layer_ptrs(net, net->params, l, W, b, fi, fo);
+    const long cnt = static_cast<long>(fi) * fo + fo;
+    mlp::init_layer<<<mlp::nblk(cnt), 256, 0, s>>>(net->params, off, fi, fo, seed);
+    RI_TRY(check_launch("init_layer"));
+    off += cnt;
+  }
+  RI_HIP(hipMemsetAsync(net->m, 0, 2 * net->nparams * sizeof(float), s));
+  net->step = 0;
+  return RI_OK;
+}
+
+void ri_mlp_default_train_opts(ri_mlp_train_opts* opts) {
+  if (!opts) return;
+  opts->epochs = 30;
+  opts->batch = 4096;
+  opts->lr = 5e-4f;
+  opts->warmup = 0.05f;
+  opts->seed = 1;
+  opts->shuffle = 1;
+}
+
+int ri_mlp_train(ri_mlp* net, const float* X, const float* Y, long n, const float* X_val, const float* Y_val,
+                 long n_val, const ri_mlp_train_opts* opts, float* train_loss, float* val_loss, void* stream) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_train"));
+  ri_mlp_train_opts o;
+  ri_mlp_default_train_opts(&o);
+  if (opts) o = *opts;
+  if (!X || !Y || n <= 0 || n > (1L << 28)) {
+    set_error("ri_mlp_train: need X and Y with 1 <= n <= 2^28 rows");
+    return RI_E_ARG;
+  }
+  if (o.epochs <= 0 || o.epochs > 1000000 || o.batch <= 0 || o.batch > (1L << 24) || !(o.lr > 0.f) ||
+      !std::isfinite(o.lr) || !(o.warmup >= 0.f && o.warmup <= 1.f)) {
+    set_error("ri_mlp_train: invalid options (epochs %d, batch %ld, lr %g, warmup %g)", o.epochs, o.batch,
+              static_cast<double>(o.lr), static_cast<double>(o.warmup));
+    return RI_E_ARG;
+  }
+  if (n_val < 0 || n_val > (1L << 28) || (n_val > 0 && (!X_val || !Y_val)) || (val_loss && n_val == 0)) {
+    set_error("ri_mlp_train: invalid validation set (n_val %ld)", n_val);
+    return RI_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int d = net->d_in;
+  const long bs = std::min(o.batch, n);
+  const long steps = std::max(1L, n / o.batch);
+  const long total = static_cast<long>(o.epochs) * steps;
+  const long warm = std::max(1L, static_cast<long>(static_cast<double>(total) * static_cast<double>(o.warmup)));
+  RI_TRY(mlp::reserve(net, bs, s));
+
+  // workspace: shuffled X [n][d] and Y [n], validation outputs [n_val], loss
+  // histories [2][epochs], permutation [n]
+  const size_t nf = (o.shuffle ? static_cast<size_t>(n) * (d + 1) : 0) + static_cast<size_t>(n_val) +
+                    2 * static_cast<size_t>(o.epochs);
+  const size_t bytes = round_up(nf * sizeof(float), 256) + (o.shuffle ? static_cast<size_t>(n) * sizeof(int) : 0);
+  std::vector<int> hperm[2];
+  std::vector<float> hist(2 * static_cast<size_t>(o.epochs));
+  struct Guard {
+    void* ws = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipStream_t s;
+    ~Guard() {
+      for (hipEvent_t e : ev)
+        if (e) {
+          (void)hipEventSynchronize(e);  // the copy that reads a host permutation has finished
+          (void)hipEventDestroy(e);
+        }
+      if (ws) dev_free(ws, s);
+    }
+  } g;
+  g.s = s;
+  RI_TRY(dev_alloc(&g.ws, bytes, s));
+  float* fp = static_cast<float*>(g.ws);
+  float* Xs = fp;
+  float* Ys = Xs + (o.shuffle ? static_cast<size_t>(n) * d : 0);
+  float* yv = Ys + (o.shuffle ? n : 0);
+  float* tl = yv + n_val;
+  float* vl = tl + o.epochs;
+  int* dperm = reinterpret_cast<int*>(reinterpret_cast<char*>(g.ws) + round_up(nf * sizeof(float), 256));
+  RI_HIP(hipMemsetAsync(tl, 0, 2 * static_cast<size_t>(o.epochs) * sizeof(float), s));
+  if (o.shuffle) {
+    for (int k = 0; k < 2; ++k) {
+      hperm[k].resize(n);
+      RI_HIP(hipEventCreateWithFlags(&g.ev[k], hipEventDisableTiming));
+    }
+  }
+  unsigned long long ctr = 0;
+  long it = 0;
+  for (int ep = 0; ep < o.epochs; ++ep) {
+    const float* Xe = X;
+    const float* Ye = Y;
+    if (o.shuffle) {
+      const int k = ep & 1;
+      RI_HIP(hipEventSynchronize(g.ev[k]));  // the copy from this host buffer two epochs ago is done
+      mlp::shuffle(hperm[k], n, o.seed, &ctr);
+      RI_HIP(hipMemcpyAsync(dperm, hperm[k].data(), static_cast<size_t>(n) * sizeof(int), hipMemcpyHostToDevice, s));
+      RI_HIP(hipEventRecord(g.ev[k], s));
+      mlp::gather_rows<<<mlp::nblk(n * (d + 1)), 256, 0, s>>>(X, Y, dperm, n, d, Xs, Ys);
+      RI_TRY(check_launch("gather_rows"));
+      Xe = Xs;
+      Ye = Ys;
+    }
+    for (long st = 0; st < steps; ++st, ++it) {
+      const long r0 = st * bs;
+      RI_TRY(mlp::gradient(net, Xe + r0 * d, Ye + r0, bs, net->grad, s));
+      mlp::add_scaled<<<1, 64, 0, s>>>(tl + ep, mlp::carve(net).loss, 1.f / static_cast<float>(steps));
+      RI_TRY(check_launch("add_scaled"));
+      RI_TRY(mlp::adam_step(net, mlp::schedule(o.lr, it, warm, total), s));
+    }
+    if (n_val > 0) {
+      for (long r0 = 0; r0 < n_val; r0 += bs) {
+        const long nn = std::min(bs, n_val - r0);
+        RI_TRY(mlp::forward(net, X_val + r0 * d, nn, yv + r0, s));
+      }
+      mlp::Scr c = mlp::carve(net);
+      mlp::mse_stage1<<<mlp::LB, 256, 0, s>>>(yv, Y_val, n_val, nullptr, c.lpart);
+      mlp::mse_stage2<<<1, 256, 0, s>>>(c.lpart, n_val, vl + ep);
+      RI_TRY(check_launch("validation loss"));
+    }
+  }
+  if (train_loss || val_loss) {
+    RI_HIP(hipMemcpyAsync(hist.data(), tl, hist.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    RI_HIP(hipStreamSynchronize(s));
+    if (train_loss) memcpy(train_loss, hist.data(), o.epochs * sizeof(float));
+    if (val_loss) memcpy(val_loss, hist.data() + o.epochs, o.epochs * sizeof(float));
+    for (int ep = 0; ep < o.epochs; ++ep)
+      if (!std::isfinite(hist[ep]) || (val_loss && !std::isfinite(hist[o.epochs + ep]))) {
+        set_error("ri_mlp_train: loss is not finite after epoch %d", ep + 1);
+        return RI_E_NUMERIC;
+      }
   }
   return RI_OK;
 }

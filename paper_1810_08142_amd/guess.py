@@ -61,16 +61,17 @@ def build_dataset(shapes, per_system: int, seed: int, scale="naux", tol: float =
 
 
 def train(X, Y, hidden=256, layers=2, epochs=30, batch=4096, lr=5e-4, seed=0, holdout=0.05, log=None):
-    """Fit the network to (X, Y) with the GPU kernels; returns (net, history).
+    """Fit the network to (X, Y) with the library's training loop; returns (net, history).
 
     Features are standardised and the target divided by its standard deviation
-    (both stored in the network); a held-out fraction measures the fit."""
+    (both stored in the network); a held-out fraction measures the fit after each
+    epoch (history: held-out loss per epoch)."""
     import torch
 
     from . import mlp
     rng = np.random.default_rng(seed + 1)
     perm0 = rng.permutation(X.shape[0])
-    nho = int(holdout * X.shape[0])
+    nho = max(1, int(holdout * X.shape[0]))
     ho, tr = perm0[:nho], perm0[nho:]
     mean = X[tr].mean(axis=0).astype(np.float32)
     std = X[tr].std(axis=0).astype(np.float32)
@@ -79,31 +80,18 @@ def train(X, Y, hidden=256, layers=2, epochs=30, batch=4096, lr=5e-4, seed=0, ho
     Xn = ((X - mean) / std).astype(np.float32)
     Yn = (Y / y_scale).astype(np.float32)
     net = mlp.Net(X.shape[1], hidden, layers)
-    net.set_params(mlp.init_params(X.shape[1], hidden, layers, seed))
+    net.init(seed)
     net.set_scaling(mean, std, y_scale)
-    Xho = torch.from_numpy(Xn[ho]).to("cuda")
-    Yho = Yn[ho]
-    n = tr.size
-    steps = max(1, n // batch)
-    total = epochs * steps
-    warm = max(1, total // 20)
-    hist = []
-    it = 0
-    for ep in range(epochs):
-        perm = tr[rng.permutation(n)]
-        Xd = torch.from_numpy(Xn[perm]).to("cuda")
-        Yd = torch.from_numpy(Yn[perm]).to("cuda")
-        for st in range(steps):
-            # linear warm-up, then cosine decay
-            lr_t = lr * min(1.0, (it + 1) / warm) * 0.5 * (1.0 + np.cos(np.pi * it / total))
-            net.train_step(Xd[st * batch:(st + 1) * batch], Yd[st * batch:(st + 1) * batch], lr_t, want_loss=False)
-            it += 1
-        yho = net.forward(Xho).cpu().numpy()
-        ho_loss = float(np.mean((yho - Yho) ** 2))
-        hist.append(ho_loss)
-        if log:
-            log(f"  epoch {ep + 1}/{epochs}: held-out loss {ho_loss:.4e} (target variance 1)")
-    return net, hist
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    t0 = time.perf_counter()
+    tl, vl = net.train(dev(Xn[tr]), dev(Yn[tr]), dev(Xn[ho]), dev(Yn[ho]), epochs=epochs, batch=batch, lr=lr,
+                       seed=seed + 2)
+    if log:
+        for ep in range(epochs):
+            log(f"  epoch {ep + 1}/{epochs}: mean batch loss {tl[ep]:.4e}, held-out loss {vl[ep]:.4e} "
+                "(target variance 1)")
+        log(f"  training: {time.perf_counter() - t0:.1f} s")
+    return net, [float(x) for x in vl]
 
 
 def evaluate(net, config="c5", scale="naux", precision="fp64", tol=1e-8, log=None, polish_residual=0.0,

@@ -88,6 +88,37 @@ class Net:
                    "ri_mlp_train_step")
         return loss.value if want_loss else None
 
+    def init(self, seed: int, stream=None):
+        """Seeded starting parameters drawn on the device (ri_mlp_init)."""
+        _lib.check(_lib.lib().ri_mlp_init(self._h, int(seed), _stream(stream)), "ri_mlp_init")
+
+    def train(self, X: torch.Tensor, Y: torch.Tensor, X_val: torch.Tensor | None = None,
+              Y_val: torch.Tensor | None = None, epochs: int = 30, batch: int = 4096, lr: float = 5e-4,
+              warmup: float = 0.05, seed: int = 1, shuffle: bool = True, stream=None):
+        """The whole training loop in the library (ri_mlp_train).
+
+        Returns (train_loss, val_loss): per-epoch mean batch loss and validation loss
+        (None without a validation set)."""
+        n = X.shape[0]
+        _need(X, "X", (n, self.d_in), torch.float32)
+        _need(Y, "Y", (n,), torch.float32)
+        nv = 0
+        if X_val is not None:
+            nv = X_val.shape[0]
+            _need(X_val, "X_val", (nv, self.d_in), torch.float32)
+            _need(Y_val, "Y_val", (nv,), torch.float32)
+        o = _lib.RIMlpTrainOpts()
+        _lib.lib().ri_mlp_default_train_opts(ctypes.byref(o))
+        o.epochs, o.batch, o.lr, o.warmup = int(epochs), int(batch), float(lr), float(warmup)
+        o.seed, o.shuffle = int(seed), 1 if shuffle else 0
+        tl = np.zeros(o.epochs, dtype=np.float32)
+        vl = np.zeros(o.epochs, dtype=np.float32)
+        _lib.check(_lib.lib().ri_mlp_train(self._h, X.data_ptr(), Y.data_ptr(), n,
+                                           X_val.data_ptr() if nv else None, Y_val.data_ptr() if nv else None, nv,
+                                           ctypes.byref(o), _fp(tl), _fp(vl) if nv else None, _stream(stream)),
+                   "ri_mlp_train")
+        return tl, (vl if nv else None)
+
     @property
     def handle(self):
         """The ri_mlp handle (an integer address) for the C ABI."""

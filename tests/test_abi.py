@@ -50,3 +50,16 @@ def test_argument_checks_before_any_device_work():
     assert L.ri_ppl_workspace_bytes(2, 20, 8, 0) > 0
     # overlapping output and input
     assert L.ri_ppl(4096, 8192, 2, 3, 4, 8192, None) == 2
+
+
+def test_mlp_training_options_and_checks():
+    from paper_1810_08142_amd import _lib
+    L = _lib.lib()
+    o = _lib.RIMlpTrainOpts()
+    L.ri_mlp_default_train_opts(ctypes.byref(o))
+    assert (o.epochs, o.batch, o.shuffle, o.seed) == (30, 4096, 1, 1)
+    assert o.lr == pytest.approx(5e-4) and o.warmup == pytest.approx(0.05)
+    assert ctypes.sizeof(o) == 40  # int, long, float, float, u64, int (LP64 padding)
+    assert L.ri_mlp_train(None, 8, 16, 10, None, None, 0, None, None, None, None) == 1
+    assert b"null network" in L.ri_last_error_msg()
+    assert L.ri_mlp_init(None, 3, None) == 1

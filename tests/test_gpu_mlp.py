@@ -136,3 +136,119 @@ def test_trained_guess_cuts_iterations_on_held_out_system():
     # the same CCSD solution (several exist), reached in fewer iterations
     assert abs(res["delta_e_corr"]) <= 1e-8 and res["max_abs_delta_t2"] <= 1e-6
     assert res["learned_guess"]["iterations"] < res["mp2_guess"]["iterations"]
+
+
+# SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), output c of the stream seeded
+# with `seed`, written here from its definition for the test.
+_M64 = (1 << 64) - 1
+
+
+def _splitmix(seed, c):
+    c = np.asarray(c, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (c + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def _fisher_yates(n, seed, ctr):
+    xs = _splitmix(seed, np.arange(ctr, ctr + n - 1, dtype=np.uint64)).tolist()
+    perm = list(range(n))
+    for k, i in enumerate(range(n - 1, 0, -1)):
+        j = (int(xs[k]) * (i + 1)) >> 64
+        perm[i], perm[j] = perm[j], perm[i]
+    return np.array(perm), ctr + n - 1
+
+
+def test_seeded_init_is_box_muller_of_splitmix():
+    from paper_1810_08142_amd import mlp
+    d_in, hidden, layers, seed = 8, 64, 2, 77
+    net = mlp.Net(d_in, hidden, layers)
+    net.init(seed)
+    got = net.get_params()
+    ref, off = [], 0
+    dims = [d_in] + [hidden] * layers + [1]
+    for k in range(len(dims) - 1):
+        nw = dims[k] * dims[k + 1]
+        i = np.arange(off, off + nw, dtype=np.uint64)
+        u1 = ((_splitmix(seed, 2 * i) >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * 2.0**-53
+        u2 = (_splitmix(seed, 2 * i + np.uint64(1)) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+        ref.append(np.sqrt(-2.0 * np.log(u1)) * np.cos(2 * np.pi * u2) / np.sqrt(dims[k]))
+        ref.append(np.zeros(dims[k + 1]))
+        off += nw + dims[k + 1]
+    ref = np.concatenate(ref).astype(np.float32)
+    assert got.size == ref.size
+    np.testing.assert_allclose(got, ref, rtol=2e-6, atol=1e-7)
+    # the hidden-to-hidden weights are N(0, 1/64)
+    w = got[d_in * hidden + hidden:][:hidden * hidden] * np.sqrt(hidden)
+    assert abs(w.mean()) < 0.05 and abs(w.std() - 1.0) < 0.05
+    other = mlp.Net(d_in, hidden, layers)
+    other.init(seed + 1)
+    assert not np.array_equal(other.get_params(), got)
+
+
+@pytest.mark.parametrize("shuffle", [True, False])
+def test_library_training_loop_equals_its_steps(shuffle):
+    """ri_mlp_train (shuffle, batches, warm-up + cosine schedule, validation) gives
+    bit for bit the parameters of the same steps taken one ri_mlp_train_step at a
+    time, with the permutation and learning rates computed here from their
+    definitions; 2000 rows in batches of 256 leave a ragged 208-row remainder."""
+    import math
+
+    import torch
+    from paper_1810_08142_amd import mlp
+    n, nv, batch, epochs, seed = 2000, 300, 256, 3, 5
+    lr, warmup = np.float32(3e-3), np.float32(0.1)
+    X = draw_matrix((n, 8), 21).astype(np.float32)
+    Y = (np.sin(X[:, 0]) + 0.3 * X[:, 1] * X[:, 3]).astype(np.float32)
+    Xv = draw_matrix((nv, 8), 22).astype(np.float32)
+    Yv = (np.sin(Xv[:, 0]) + 0.3 * Xv[:, 1] * Xv[:, 3]).astype(np.float32)
+    a = mlp.Net(8, 64, 2)
+    a.init(3)
+    tl, vl = a.train(dev(X), dev(Y), dev(Xv), dev(Yv), epochs=epochs, batch=batch, lr=float(lr),
+                     warmup=float(warmup), seed=seed, shuffle=shuffle)
+    b = mlp.Net(8, 64, 2)
+    b.init(3)
+    steps = n // batch
+    total = epochs * steps
+    warm = max(1, int(total * float(warmup)))
+    ctr, it = 0, 0
+    tl_ref, vl_ref = [], []
+    for ep in range(epochs):
+        perm = np.arange(n)
+        if shuffle:
+            perm, ctr = _fisher_yates(n, seed, ctr)
+        Xe, Ye = dev(X[perm]), dev(Y[perm])
+        acc = np.float32(0)
+        for st in range(steps):
+            rate = float(lr) * min(1.0, (it + 1) / warm) * 0.5 * (1.0 + math.cos(math.pi * it / total))
+            loss = b.train_step(Xe[st * batch:(st + 1) * batch], Ye[st * batch:(st + 1) * batch], rate)
+            acc = np.float32(acc + np.float32(1.0 / steps) * np.float32(loss))
+            it += 1
+        tl_ref.append(acc)
+        yv = host(b.forward(dev(Xv))).astype(np.float64)
+        vl_ref.append(np.mean((yv - Yv) ** 2))
+    torch.cuda.synchronize()
+    assert np.array_equal(a.get_params(), b.get_params())
+    np.testing.assert_allclose(tl, tl_ref, rtol=1e-5)
+    np.testing.assert_allclose(vl, vl_ref, rtol=1e-5)
+    assert vl[-1] < vl[0]
+
+
+def test_library_training_loop_argument_checks():
+    import torch
+    from paper_1810_08142_amd import _lib, mlp
+    net = mlp.Net(8, 16, 1)
+    X = dev(np.zeros((10, 8), dtype=np.float32))
+    Y = dev(np.zeros(10, dtype=np.float32))
+    with pytest.raises(_lib.RIError):
+        net.train(X, Y, epochs=0)
+    with pytest.raises(_lib.RIError):
+        net.train(X, Y, lr=0.0)
+    with pytest.raises(_lib.RIError):
+        net.train(X, Y, warmup=1.5)
+    # batch larger than the set: one step of all rows per epoch
+    tl, vl = net.train(X, Y, epochs=2, batch=64)
+    assert vl is None and tl.shape == (2,) and np.isfinite(tl).all()
+    torch.cuda.synchronize()
