@@ -66,6 +66,10 @@ int ri_last_hip_error(void);
  * Sec. II.C).  Workspace is allocated stream-ordered on `stream` and released
  * before the call returns control of it to the stream.  Deterministic: the same
  * inputs give bitwise the same R.
+ * Debug check: with the environment variable RI_PPL_CHECK_TAU set (to anything but
+ * "0") the ladder calls first measure tau with ri_tau_pair_asymmetry (synchronising
+ * the stream) and return RI_E_ARG, leaving R untouched, unless
+ * max |tau^{cd}_{ij} - tau^{dc}_{ji}| <= 1e-12 max |tau|.
  */
 int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
            void* stream);
@@ -110,6 +114,11 @@ double ri_ppl_flops(int o, int v, int naux);
  * launched) into buf, and clears the records.  RI_E_ARG if buf is too small. */
 int ri_prof_enable(int on);
 int ri_prof_report(char* buf, size_t len);
+
+/* Distance of tau [o][o][v][v] from pair symmetry (Sec. II.C):
+ * result[0] = max |tau[i][j][c][d] - tau[j][i][d][c]|, result[1] = max |tau|
+ * (host array of two doubles; NaN if tau holds one).  Synchronises stream. */
+int ri_tau_pair_asymmetry(const double* tau, int o, int v, double* result, void* stream);
 
 /* tau[i][j][a][b] = t2[i][j][a][b] + t1[i][a] t1[j][b]   (eq. pp-Ladder-01).
  * t1: [o][v], t2 and tau: [o][o][v][v]; tau may alias t2 (in place). */

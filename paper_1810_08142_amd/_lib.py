@@ -62,6 +62,7 @@ _SIGS = [
     ("ri_ppl_workspace_bytes", _c.c_size_t, [_c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_build_tau", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _dp, _dp]),
+    ("ri_tau_pair_asymmetry", _c.c_int, [_dp, _c.c_int, _c.c_int, _dblp, _dp]),
     ("ri_prof_enable", _c.c_int, [_c.c_int]),
     ("ri_prof_report", _c.c_int, [_c.c_char_p, _c.c_size_t]),
     ("ri_ccsd_default_opts", None, [_c.POINTER(RICcsdOpts)]),

@@ -689,6 +689,86 @@ static int run_typed(const Plan& p, int precision, const double* B_vv, long qs, 
 
 static size_t esize_of(int precision) { return precision == RI_PREC_FP32 ? 4 : 8; }
 
+// ---------------------------------------------------------------- pair symmetry
+// The ladder uses only the pair-symmetric part of tau (tau^{cd}_{ij} = tau^{dc}_{ji},
+// Sec. II.C).  These kernels measure how far an input is from it:
+// out = {max |tau[i][j][c][d] - tau[j][i][d][c]|, max |tau|}; NaN propagates.
+constexpr int ASYM_BLOCKS = 1024;
+__device__ inline double nan_max(double m, double x) { return (x != x || x > m) ? x : m; }
+__device__ inline void block_max2(double& a, double& b, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = a;
+  sh[256 + t] = b;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) {
+      sh[t] = nan_max(sh[t], sh[t + k]);
+      sh[256 + t] = nan_max(sh[256 + t], sh[256 + t + k]);
+    }
+    __syncthreads();
+  }
+  a = sh[0];
+  b = sh[256];
+}
+__global__ __launch_bounds__(256) void pair_asym_partial(const double* __restrict__ tau, int o, int v, double* part) {
+  __shared__ double sh[512];
+  const long vv = static_cast<long>(v) * v, n = static_cast<long>(o) * o * vv;
+  double asym = 0.0, amax = 0.0;
+  for (long x = static_cast<long>(blockIdx.x) * 256 + threadIdx.x; x < n; x += static_cast<long>(gridDim.x) * 256) {
+    const long ij = x / vv, cd = x - ij * vv;
+    const int i = static_cast<int>(ij / o), j = static_cast<int>(ij - static_cast<long>(i) * o);
+    const int c = static_cast<int>(cd / v), d = static_cast<int>(cd - static_cast<long>(c) * v);
+    const double t = tau[x];
+    const double m = tau[(static_cast<long>(j) * o + i) * vv + static_cast<long>(d) * v + c];
+    asym = nan_max(asym, fabs(t - m));
+    amax = nan_max(amax, fabs(t));
+  }
+  block_max2(asym, amax, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = asym;
+    part[2 * blockIdx.x + 1] = amax;
+  }
+}
+__global__ __launch_bounds__(256) void pair_asym_final(const double* __restrict__ part, double* out) {
+  __shared__ double sh[512];
+  double asym = 0.0, amax = 0.0;
+  for (int k = threadIdx.x; k < ASYM_BLOCKS; k += 256) {
+    asym = nan_max(asym, part[2 * k]);
+    amax = nan_max(amax, part[2 * k + 1]);
+  }
+  block_max2(asym, amax, sh);
+  if (threadIdx.x == 0) {
+    out[0] = asym;
+    out[1] = amax;
+  }
+}
+int pair_asymmetry(const double* tau, int o, int v, double* host2, hipStream_t s) {
+  void* buf = nullptr;
+  RI_TRY(dev_alloc(&buf, (2 * ASYM_BLOCKS + 2) * sizeof(double), s));
+  double* part = static_cast<double*>(buf);
+  pair_asym_partial<<<ASYM_BLOCKS, 256, 0, s>>>(tau, o, v, part);
+  pair_asym_final<<<1, 256, 0, s>>>(part, part + 2 * ASYM_BLOCKS);
+  int rc = check_launch("pair_asym");
+  if (rc == RI_OK) rc = check_hip(hipMemcpyAsync(host2, part + 2 * ASYM_BLOCKS, 2 * sizeof(double),
+                                                 hipMemcpyDeviceToHost, s), "pair_asym copy");
+  if (rc == RI_OK) rc = check_hip(hipStreamSynchronize(s), "pair_asym sync");
+  dev_free(buf, s);
+  return rc;
+}
+// RI_PPL_CHECK_TAU set (and not "0"): the ladder first checks that tau is
+// pair-symmetric to 1e-12 of its largest element and rejects it otherwise.
+int check_tau_if_asked(const double* tau, int o, int v, hipStream_t s) {
+  const char* e = getenv("RI_PPL_CHECK_TAU");
+  if (!e || !*e || (e[0] == '0' && e[1] == 0)) return RI_OK;
+  double r[2];
+  RI_TRY(pair_asymmetry(tau, o, v, r, s));
+  if (!(r[0] <= 1e-12 * r[1])) {
+    set_error("ri_ppl: tau is not pair-symmetric: max |tau_ij^cd - tau_ji^dc| = %.3e, max |tau| = %.3e", r[0], r[1]);
+    return RI_E_ARG;
+  }
+  return RI_OK;
+}
+
 }  // namespace ppl
 
 int ppl_strided(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
@@ -763,6 +843,7 @@ int ri_ppl_shard(const double* B_vv, const double* tau, int o, int v, int naux, 
     set_error("ri_ppl: workspace must be 256-byte aligned");
     return RI_E_ARG;
   }
+  RI_TRY(ppl::check_tau_if_asked(tau, o, v, s));
   if (precision == RI_PREC_BF16X3)
     return ppl::bf16x3_run(B_vv, static_cast<long>(v) * v, v, tau, o, v, naux, R, ws, ws_bytes, shard, nshards, s);
   if (ws && ws_bytes < p.bytes) {
@@ -779,6 +860,15 @@ int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, dou
 
 int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream) {
   return ri_ppl_ex(B_vv, tau, o, v, naux, R, RI_PREC_FP64, nullptr, 0, stream);
+}
+
+int ri_tau_pair_asymmetry(const double* tau, int o, int v, double* result, void* stream) {
+  clear_error();
+  if (!tau || !result || o <= 0 || v <= 0 || static_cast<long>(o) * o * v * v > (1L << 40)) {
+    set_error("ri_tau_pair_asymmetry: invalid argument");
+    return RI_E_ARG;
+  }
+  return ppl::pair_asymmetry(tau, o, v, result, static_cast<hipStream_t>(stream));
 }
 
 int ri_build_tau(const double* t1, const double* t2, int o, int v, double* tau, void* stream) {

@@ -6,6 +6,8 @@ in the library's HIP kernels.
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from . import _lib
@@ -77,3 +79,12 @@ def build_tau(t1: torch.Tensor, t2: torch.Tensor, out: torch.Tensor | None = Non
     _lib.check(_lib.lib().ri_build_tau(t1.data_ptr(), t2.data_ptr(), o, v, out.data_ptr(), _stream(stream)),
                "ri_build_tau")
     return out
+
+
+def pair_asymmetry(tau: torch.Tensor, stream=None):
+    """(max |tau^{cd}_{ij} - tau^{dc}_{ji}|, max |tau|) of tau [o][o][v][v]."""
+    o, v = tau.shape[0], tau.shape[2]
+    _need(tau, "tau", (o, o, v, v))
+    r = (ctypes.c_double * 2)()
+    _lib.check(_lib.lib().ri_tau_pair_asymmetry(tau.data_ptr(), o, v, r, _stream(stream)), "ri_tau_pair_asymmetry")
+    return r[0], r[1]

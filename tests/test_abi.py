@@ -63,3 +63,6 @@ def test_mlp_training_options_and_checks():
     assert L.ri_mlp_train(None, 8, 16, 10, None, None, 0, None, None, None, None) == 1
     assert b"null network" in L.ri_last_error_msg()
     assert L.ri_mlp_init(None, 3, None) == 1
+    r = (ctypes.c_double * 2)()
+    assert L.ri_tau_pair_asymmetry(None, 2, 3, r, None) == 1
+    assert L.ri_tau_pair_asymmetry(64, 0, 3, r, None) == 1

@@ -233,3 +233,34 @@ def test_power_of_two_scaling_is_bitwise(precision):
     _ppl().ppl(dev(s.B_vv), dev(tau), R1, precision=precision)
     _ppl().ppl(dev(s.B_vv * 4.0), dev(tau * 0.5), R2, precision=precision)  # 2^(2*2 - 1) = 8
     assert bool((R2 == 8.0 * R1).all())
+
+
+def test_pair_asymmetry_measure_and_debug_check(monkeypatch):
+    """ri_tau_pair_asymmetry returns max |tau_ij^cd - tau_ji^dc| and max |tau|
+    exactly; with RI_PPL_CHECK_TAU set the ladder rejects a tau that is not
+    pair-symmetric and leaves R untouched."""
+    import torch
+    from paper_1810_08142_amd import _lib, ppl
+    o, v, naux = 3, 21, 10
+    s = draw_system(o, v, naux, seed=8)
+    T = draw_pair_symmetric(o, v, 31, 0.01)
+    assert ppl.pair_asymmetry(dev(T)) == (0.0, float(np.abs(T).max()))
+    bad = T.copy()
+    bad[2, 0, 5, 17] += 3e-4
+    ref = np.abs(bad - bad.transpose(1, 0, 3, 2)).max()
+    asym, amax = ppl.pair_asymmetry(dev(bad))
+    assert asym == ref and amax == np.abs(bad).max()
+    nan = T.copy()
+    nan[1, 1, 3, 3] = np.nan
+    assert np.isnan(ppl.pair_asymmetry(dev(nan))[0])
+    B = dev(np.ascontiguousarray(s.B_vv))
+    monkeypatch.setenv("RI_PPL_CHECK_TAU", "1")
+    R = torch.full((o, o, v, v), 0.5, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.RIError) as ei:
+        ppl.ppl(B, dev(bad), R)
+    assert ei.value.status == 1 and "pair-symmetric" in str(ei.value)
+    assert bool((R == 0.5).all())
+    ppl.ppl(B, dev(T), R)  # a symmetric tau passes the check
+    monkeypatch.setenv("RI_PPL_CHECK_TAU", "0")
+    ppl.ppl(B, dev(bad), R)  # check off: the symmetric part is used
+    torch.cuda.synchronize()
