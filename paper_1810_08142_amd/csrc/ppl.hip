@@ -148,21 +148,34 @@ __global__ __launch_bounds__(256) void pack_tau_f32(const double* __restrict__ t
 // of the quarter and accumulates (ac|bd) and (ad|bc) as 16x16 (a, b) MFMA tiles.
 // LDS holds, per KC-wide Q chunk, Bc for the 16 c/d rows x (16 a + 16 b) columns.
 // grid (nbp*4, slab_pairs), block 512
-template <class T>
+// D: the workgroups of diagonal ab block pairs (Ab == Bb), blockIdx.y counting them
+// from block Ab = diag_y0; otherwise blockIdx.y is the slab's pair and diagonal pairs
+// exit at once.  In a diagonal pair a and b run over the same block, so the (ad|bc)
+// tile is the transpose of the (ac|bd) tile: only the latter is built, and the
+// epilogue reads it back transposed through LDS.
+template <class T, bool D>
 __device__ __forceinline__ void build_body(const T* __restrict__ Bc, int naux_p, int vp, long slab0, long slab_M,
-                                           int want_minus, T* __restrict__ Wp, T* __restrict__ Wm) {
+                                           int want_minus, int diag_y0, T* __restrict__ Wp, T* __restrict__ Wm) {
   typedef Mfma<T> MF;
   typedef typename MF::vec_t vec_t;
   constexpr int VEC = 16 / sizeof(T);          // elements per 16-byte load
   constexpr int EV = 32 / VEC;                 // loads per (x, k) row of 32 e
   constexpr int NV = 16 * KC * 32 / (512 * VEC);  // loads per thread per chunk
   __shared__ T lds[2][16][KC][32];  // [buf][x: 8 c then 8 d][k][e: 16 a then 16 b]
+  static_assert(2 * 16 * KC * 32 >= 8 * 8 * 256, "the staging buffer holds the transposed tiles");
   const int quarter = blockIdx.x & 3;
   const long pcd = blockIdx.x >> 2;
-  const long pab_loc = blockIdx.y;
   int Cb, Db, Ab, Bb;
   tri_decode(pcd, Cb, Db);
-  tri_decode(slab0 + pab_loc, Ab, Bb);
+  long pab_loc;
+  if constexpr (D) {
+    Ab = Bb = diag_y0 + static_cast<int>(blockIdx.y);
+    pab_loc = static_cast<long>(Ab) * (Ab + 3) / 2 - slab0;
+  } else {
+    pab_loc = blockIdx.y;
+    tri_decode(slab0 + pab_loc, Ab, Bb);
+    if (Ab == Bb) return;  // built by the diagonal launch (uniform over the workgroup)
+  }
   const int c_base = Cb * TB + (quarter >> 1) * 8;
   const int d_base = Db * TB + (quarter & 1) * 8;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -184,15 +197,6 @@ __device__ __forceinline__ void build_body(const T* __restrict__ Bc, int naux_p,
   T* lds0 = &lds[0][0][0][0];
   constexpr int LBUF = 16 * KC * 32;
 
-  typename MF::acc_t acc1[2][4], acc2[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      acc1[i][j] = MF::zero();
-      acc2[i][j] = MF::zero();
-    }
-
   const int xc0 = (w >> 1) * 2, xd0 = 8 + (w & 1) * 4;
   const int m = lane & 15, kq = lane >> 4;
   const int nchunks = naux_p / KC;
@@ -200,80 +204,136 @@ __device__ __forceinline__ void build_body(const T* __restrict__ Bc, int naux_p,
   // half holds only c > d slots, whose packed amplitudes are zero: its W entries are
   // written as zeros without the build (uniform over the workgroup).
   const bool skip = Cb == Db && quarter == 2;
-  if (!skip) {
-    vec_t stage[NV];
+  const size_t col0 = static_cast<size_t>(pab_loc) * 256;
+
+  {
+    constexpr int NA2 = D ? 1 : 2;  // (ad|bc) accumulators are not needed when D
+    typename MF::acc_t acc1[2][4], acc2[NA2][4];
 #pragma unroll
-    for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r]);
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(lds0 + loff[r]) = stage[r];
-    __syncthreads();
-    for (int ch = 0; ch < nchunks; ++ch) {
-      const int buf = ch & 1;
-      const bool more = ch + 1 < nchunks;
-      if (more) {
-        const size_t qo = static_cast<size_t>(ch + 1) * qstride;
+      for (int j = 0; j < 4; ++j) acc1[i][j] = MF::zero();
 #pragma unroll
-        for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r] + qo);
-      }
+    for (int i = 0; i < NA2; ++i)
 #pragma unroll
-      for (int s = 0; s < KC / 4; ++s) {
-        const int kk = 4 * s + kq;
-        T a_c[2], b_c[2], a_d[4], b_d[4];
+      for (int j = 0; j < 4; ++j) acc2[i][j] = MF::zero();
+    if (!skip) {
+      vec_t stage[NV];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          a_c[i] = lds[buf][xc0 + i][kk][m];
-          b_c[i] = lds[buf][xc0 + i][kk][16 + m];
+      for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r]);
+#pragma unroll
+      for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(lds0 + loff[r]) = stage[r];
+      __syncthreads();
+      for (int ch = 0; ch < nchunks; ++ch) {
+        const int buf = ch & 1;
+        const bool more = ch + 1 < nchunks;
+        if (more) {
+          const size_t qo = static_cast<size_t>(ch + 1) * qstride;
+#pragma unroll
+          for (int r = 0; r < NV; ++r) stage[r] = *reinterpret_cast<const vec_t*>(Bc + goff[r] + qo);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          a_d[j] = lds[buf][xd0 + j][kk][m];
-          b_d[j] = lds[buf][xd0 + j][kk][16 + m];
-        }
+        for (int s = 0; s < KC / 4; ++s) {
+          const int kk = 4 * s + kq;
+          if constexpr (D) {
+            T a_c[2], b_d[4];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i) a_c[i] = lds[buf][xc0 + i][kk][m];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            acc1[i][j] = MF::mma(a_c[i], b_d[j], acc1[i][j]);  // (ac|bd)
-            acc2[i][j] = MF::mma(a_d[j], b_c[i], acc2[i][j]);  // (ad|bc)
+            for (int j = 0; j < 4; ++j) b_d[j] = lds[buf][xd0 + j][kk][16 + m];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc1[i][j] = MF::mma(a_c[i], b_d[j], acc1[i][j]);  // (ac|bd)
+          } else {
+            T a_c[2], b_c[2], a_d[4], b_d[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+              a_c[i] = lds[buf][xc0 + i][kk][m];
+              b_c[i] = lds[buf][xc0 + i][kk][16 + m];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              a_d[j] = lds[buf][xd0 + j][kk][m];
+              b_d[j] = lds[buf][xd0 + j][kk][16 + m];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                acc1[i][j] = MF::mma(a_c[i], b_d[j], acc1[i][j]);      // (ac|bd)
+                acc2[i % NA2][j] = MF::mma(a_d[j], b_c[i], acc2[i % NA2][j]);  // (ad|bc)
+              }
           }
-      }
-      if (more) {
-        T* dst = lds0 + (buf ^ 1) * LBUF;
+        }
+        if (more) {
+          T* dst = lds0 + (buf ^ 1) * LBUF;
 #pragma unroll
-        for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(dst + loff[r]) = stage[r];
+          for (int r = 0; r < NV; ++r) *reinterpret_cast<vec_t*>(dst + loff[r]) = stage[r];
+        }
+        __syncthreads();
       }
+    }  // !skip
+
+    // each wave's own 8 x 256 elements of the (now idle) staging buffer hold its
+    // (ac|bd) tiles, element (a, b) of a tile at a*16 + (b ^ a)
+    T* tw = lds0 + w * (8 * 256);
+    if constexpr (D) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int a_in = MF::drow(r, lane), b_in = lane & 15;
+            tw[(i * 4 + j) * 256 + a_in * 16 + (b_in ^ a_in)] = acc1[i][j][r];
+          }
       __syncthreads();
     }
-  }  // !skip
 
-  // epilogue: W+-[slot][ab slot]; element r of a lane is row a_in = drow(r, lane),
-  // column b_in = lane & 15 of the (a, b) tile.
-  const size_t col0 = static_cast<size_t>(pab_loc) * 256;
+    // epilogue: W+-[slot][ab slot]; element r of a lane is row a_in = drow(r, lane),
+    // column b_in = lane & 15 of the (a, b) tile.
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c_in = (quarter >> 1) * 8 + xc0 + i;
-      const int d_in = (quarter & 1) * 8 + (xd0 - 8) + j;
-      const size_t row = (static_cast<size_t>(pcd) * 256 + c_in * 16 + d_in) * slab_M + col0;
+      for (int j = 0; j < 4; ++j) {
+        const int c_in = (quarter >> 1) * 8 + xc0 + i;
+        const int d_in = (quarter & 1) * 8 + (xd0 - 8) + j;
+        const size_t row = (static_cast<size_t>(pcd) * 256 + c_in * 16 + d_in) * slab_M + col0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a_in = MF::drow(r, lane), b_in = lane & 15;
-        const T v1 = acc1[i][j][r], v2 = acc2[i][j][r];
-        Wp[row + a_in * 16 + b_in] = v1 + v2;
-        if (want_minus) Wm[row + a_in * 16 + b_in] = v1 - v2;
+        for (int r = 0; r < 4; ++r) {
+          const int a_in = MF::drow(r, lane), b_in = lane & 15;
+          const T v1 = acc1[i][j][r];
+          T v2;
+          if constexpr (D)
+            v2 = tw[(i * 4 + j) * 256 + b_in * 16 + (a_in ^ b_in)];  // (ac|bd)[b][a]
+          else
+            v2 = acc2[i][j][r];
+          Wp[row + a_in * 16 + b_in] = v1 + v2;
+          if (want_minus) Wm[row + a_in * 16 + b_in] = v1 - v2;
+        }
       }
-    }
+  }
 }
 __global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc, int naux_p, int vp, long slab0,
-                                                   long slab_M, int want_minus, double* __restrict__ Wp,
+                                                   long slab_M, int want_minus, int diag_y0, double* __restrict__ Wp,
                                                    double* __restrict__ Wm) {
-  build_body<double>(Bc, naux_p, vp, slab0, slab_M, want_minus, Wp, Wm);
+  build_body<double, false>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, Wp, Wm);
+}
+__global__ __launch_bounds__(512) void build_w_f64_diag(const double* __restrict__ Bc, int naux_p, int vp, long slab0,
+                                                        long slab_M, int want_minus, int diag_y0,
+                                                        double* __restrict__ Wp, double* __restrict__ Wm) {
+  build_body<double, true>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, Wp, Wm);
 }
 __global__ __launch_bounds__(512) void build_w_f32(const float* __restrict__ Bc, int naux_p, int vp, long slab0,
-                                                   long slab_M, int want_minus, float* __restrict__ Wp,
+                                                   long slab_M, int want_minus, int diag_y0, float* __restrict__ Wp,
                                                    float* __restrict__ Wm) {
-  build_body<float>(Bc, naux_p, vp, slab0, slab_M, want_minus, Wp, Wm);
+  build_body<float, false>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, Wp, Wm);
+}
+__global__ __launch_bounds__(512) void build_w_f32_diag(const float* __restrict__ Bc, int naux_p, int vp, long slab0,
+                                                        long slab_M, int want_minus, int diag_y0,
+                                                        float* __restrict__ Wp, float* __restrict__ Wm) {
+  build_body<float, true>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, Wp, Wm);
 }
 
 // ---------------------------------------------------------------- 3b. contract
@@ -549,6 +609,7 @@ struct K64 {
   static constexpr const char* relayout = "relayout_b_f64";
   static constexpr const char* pack = "pack_tau_f64";
   static constexpr const char* build = "build_w_f64";
+  static constexpr const char* build_diag = "build_w_f64_diag";
   static constexpr const char* contract = "contract_f64";
   static constexpr const char* unpack = "unpack_f64";
   static void relayout_k(dim3 g, hipStream_t s, const double* B, long qs, long rs, int v, int naux, int vp, int np,
@@ -559,7 +620,11 @@ struct K64 {
     pack_tau_f64<<<g, 256, 0, s>>>(tau, o, v, ncol, sign, out);
   }
   static void build_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, T* Wp, T* Wm) {
-    build_w_f64<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, Wp, Wm);
+    build_w_f64<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, 0, Wp, Wm);
+  }
+  static void build_diag_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, int y0,
+                           T* Wp, T* Wm) {
+    build_w_f64_diag<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, y0, Wp, Wm);
   }
   template <int NTW>
   static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C, long kz,
@@ -572,6 +637,7 @@ struct K32 {
   static constexpr const char* relayout = "relayout_b_f32";
   static constexpr const char* pack = "pack_tau_f32";
   static constexpr const char* build = "build_w_f32";
+  static constexpr const char* build_diag = "build_w_f32_diag";
   static constexpr const char* contract = "contract_f32";
   static constexpr const char* unpack = "unpack_f32";
   static void relayout_k(dim3 g, hipStream_t s, const double* B, long qs, long rs, int v, int naux, int vp, int np,
@@ -582,7 +648,11 @@ struct K32 {
     pack_tau_f32<<<g, 256, 0, s>>>(tau, o, v, ncol, sign, out);
   }
   static void build_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, T* Wp, T* Wm) {
-    build_w_f32<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, Wp, Wm);
+    build_w_f32<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, 0, Wp, Wm);
+  }
+  static void build_diag_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, int y0,
+                           T* Wp, T* Wm) {
+    build_w_f32_diag<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, y0, Wp, Wm);
   }
   template <int NTW>
   static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C, long kz,
@@ -646,16 +716,25 @@ static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const d
     if ((slab0 / p.slab_bp) % nshards != shard) continue;  // another shard's slab
     const long npairs = (p.nbp - slab0) < p.slab_bp ? (p.nbp - slab0) : p.slab_bp;
     const long M = npairs * 256;
-    double le, lt;
-    count_pairs(p.v, slab0, npairs, le, lt);
+    double le, lt, ld;
+    count_pairs(p.v, slab0, npairs, le, lt, ld);
+    int dy0, ndiag;
+    diag_pairs(slab0, npairs, dy0, ndiag);
     long kzp = 0, kzm = 0;
     const int zp = contract_splits(p.NP, p.ntw_p, M, p.K, kzp);
     const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, p.K, kzm) : 1;
     {
-      // per valid (a <= b): the v x v matrix (ac|bd) over all c, d, naux products each
-      ProfScope ps(s, KS::build, 2.0 * p.naux * vv * le);
+      // per valid (a <= b): the v x v matrix (ac|bd) over all c, d, naux products each;
+      // off-diagonal and diagonal ab block pairs in two launches
+      ProfScope ps(s, KS::build, 2.0 * p.naux * vv * (le - ld));
       KS::build_k(dim3(p.nbp * 4, npairs), s, Bc, p.naux_p, p.vp, slab0, p.slab_M, p.pm > 0 ? 1 : 0, Wp, Wm);
       RI_TRY(check_launch(KS::build));
+    }
+    if (ndiag > 0) {
+      ProfScope ps(s, KS::build_diag, 2.0 * p.naux * vv * ld);
+      KS::build_diag_k(dim3(p.nbp * 4, ndiag), s, Bc, p.naux_p, p.vp, slab0, p.slab_M, p.pm > 0 ? 1 : 0, dy0, Wp,
+                       Wm);
+      RI_TRY(check_launch(KS::build_diag));
     }
     {
       ProfScope ps(s, KS::contract, 2.0 * (le * pv * p.po + lt * pvm * p.pm));

@@ -156,18 +156,31 @@ __global__ __launch_bounds__(256) void pack_tau_bf16_kernel(const double* __rest
 // LDS per buffer: 16-byte runs [x 16][hl 2][e 32][run 4], run index XOR-swizzled with
 // sw4(e) so that the lanes of one ds_read_b128 hit distinct banks.
 // grid (nbp*4, slab_pairs), block 512
-__global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
-                                                      int Qp, int vp, long slab0, long K, int want_minus,
-                                                      uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
-                                                      uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
+// D: the workgroups of diagonal ab block pairs (Ab == Bb), blockIdx.y counting them
+// from block Ab = diag_y0; otherwise blockIdx.y is the slab's pair and diagonal pairs
+// exit at once.  In a diagonal pair the (ad|bc) tile is the transpose of the (ac|bd)
+// tile: only the latter is built, and the epilogue reads it back through LDS.
+template <bool D>
+__device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
+                                                  int Qp, int vp, long slab0, long K, int want_minus, int diag_y0,
+                                                  uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
+                                                  uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
   constexpr int RUNS = 16 * 2 * 32 * 4;  // 4096 runs = 64 KB per buffer
   __shared__ u32x4_t lds[2 * RUNS];
+  static_assert(2 * RUNS * 4 >= 8 * 8 * 256, "the staging buffer holds the transposed tiles");
   const int quarter = blockIdx.x & 3;
   const long pcd = blockIdx.x >> 2;
-  const long pab_loc = blockIdx.y;
   int Cb, Db, Ab, Bb;
   tri_decode(pcd, Cb, Db);
-  tri_decode(slab0 + pab_loc, Ab, Bb);
+  long pab_loc;
+  if constexpr (D) {
+    Ab = Bb = diag_y0 + static_cast<int>(blockIdx.y);
+    pab_loc = static_cast<long>(Ab) * (Ab + 3) / 2 - slab0;
+  } else {
+    pab_loc = blockIdx.y;
+    tri_decode(slab0 + pab_loc, Ab, Bb);
+    if (Ab == Bb) return;  // built by the diagonal launch (uniform over the workgroup)
+  }
   const int c_base = Cb * TB + (quarter >> 1) * 8;
   const int d_base = Db * TB + (quarter & 1) * 8;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -222,6 +235,19 @@ __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict
         const u32x4_t v = lds[base + ((x * 2 + hl) * 32 + e_off + fe) * 4 + fsw];
         return __builtin_bit_cast(bf16x8_t, v);
       };
+      if constexpr (D) {
+        bf16x8_t ac[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int hl = 0; hl < 2; ++hl) ac[i][hl] = frag(xc0 + i, hl, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bf16x8_t bdh = frag(xd0 + j, 0, 16), bdl = frag(xd0 + j, 1, 16);
+#pragma unroll
+          for (int i = 0; i < 2; ++i) o1[i][j] = mfma3(ac[i][0], ac[i][1], bdh, bdl, o1[i][j]);  // (ac|bd)
+        }
+      } else {
       bf16x8_t ac[2][2], bc[2][2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -240,6 +266,7 @@ __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict
           o2[i][j] = mfma3_mirror(adh, adl, bc[i][0], bc[i][1], o2[i][j]);  // (ad|bc)
         }
       }
+      }  // diag
       if (more) {
         const int nb = ((st + 1) & 1) * RUNS;
 #pragma unroll
@@ -248,6 +275,32 @@ __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict
       __syncthreads();
     }
   }  // !skip
+
+  if constexpr (D) {
+    // (ad|bc)[a][b] = (ac|bd)[b][a]: each wave stores its eight (ac|bd) tiles in its own
+    // 8 KB of the (now idle) staging buffer, element (a, b) at a*16 + (b ^ a), and reads
+    // them back transposed
+    float* tw = reinterpret_cast<float*>(lds) + w * (8 * 256);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a_in = 4 * (lane >> 4) + r, b_in = lane & 15;
+          tw[(i * 4 + j) * 256 + a_in * 16 + (b_in ^ a_in)] = o1[i][j][r];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a_in = 4 * (lane >> 4) + r, b_in = lane & 15;
+          o2[i][j][r] = tw[(i * 4 + j) * 256 + b_in * 16 + (a_in ^ b_in)];
+        }
+  }
 
   // epilogue: lane holds (a_in = 4*(lane>>4) + r, b_in = lane&15) for the wave's 8 slots
   const size_t slot0 = static_cast<size_t>(pcd) * 256 + quarter * 64 + w * 8;
@@ -282,6 +335,20 @@ __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict
       *reinterpret_cast<u32x4_t*>(Wml + row * K + slot0) = l;
     }
   }
+}
+
+__global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
+                                                      int Qp, int vp, long slab0, long K, int want_minus,
+                                                      uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
+                                                      uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
+  build_bf16x3_body<false>(Bh, Bl, Qp, vp, slab0, K, want_minus, 0, Wph, Wpl, Wmh, Wml);
+}
+__global__ __launch_bounds__(512) void build_w_bf16x3_diag(const uint16_t* __restrict__ Bh,
+                                                           const uint16_t* __restrict__ Bl, int Qp, int vp, long slab0,
+                                                           long K, int want_minus, int diag_y0,
+                                                           uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
+                                                           uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
+  build_bf16x3_body<true>(Bh, Bl, Qp, vp, slab0, K, want_minus, diag_y0, Wph, Wpl, Wmh, Wml);
 }
 
 // ---------------------------------------------------------------- contract
@@ -555,16 +622,24 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
       if ((slab0 / p.slab_bp) % nshards != shard) continue;  // another shard's slab
       const long npairs = std::min(p.slab_bp, p.nbp - slab0);
       const long M = npairs * 256;
-      double le, lt;
-      count_pairs(v, slab0, npairs, le, lt);
+      double le, lt, ld;
+      count_pairs(v, slab0, npairs, le, lt, ld);
+      int dy0, ndiag;
+      diag_pairs(slab0, npairs, dy0, ndiag);
       long kzp = 0, kzm = 0;
       const int zp = contract_splits(p.NP, p.ntw_p, M, p.K, kzp);
       const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, p.K, kzm) : 1;
-      {
-        ProfScope ps(s, "build_w_bf16x3", 2.0 * naux * vv * le);
+      {  // off-diagonal and diagonal ab block pairs in two launches
+        ProfScope ps(s, "build_w_bf16x3", 2.0 * naux * vv * (le - ld));
         build_w_bf16x3<<<dim3(p.nbp * 4, npairs), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K, p.pm > 0 ? 1 : 0,
                                                               Wph, Wpl, Wmh, Wml);
         if ((rc = check_launch("build_w_bf16x3"))) break;
+      }
+      if (ndiag > 0) {
+        ProfScope ps(s, "build_w_bf16x3_diag", 2.0 * naux * vv * ld);
+        build_w_bf16x3_diag<<<dim3(p.nbp * 4, ndiag), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K,
+                                                                   p.pm > 0 ? 1 : 0, dy0, Wph, Wpl, Wmh, Wml);
+        if ((rc = check_launch("build_w_bf16x3_diag"))) break;
       }
       {
         ProfScope ps(s, "contract_bf16x3", 2.0 * (le * pv * p.po + lt * pvm * p.pm));

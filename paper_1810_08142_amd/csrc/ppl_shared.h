@@ -66,9 +66,10 @@ inline long env_long(const char* name, long dflt) {
   return (end && *end == 0 && x > 0) ? x : dflt;
 }
 
-// Valid (a <= b) and (a < b) virtual pairs inside block pairs [p0, p0 + n).
-inline void count_pairs(int v, long p0, long n, double& le, double& lt) {
-  le = lt = 0;
+// Valid (a <= b) and (a < b) virtual pairs inside block pairs [p0, p0 + n), and the
+// (a <= b) pairs among them that lie in diagonal block pairs (X == Y).
+inline void count_pairs(int v, long p0, long n, double& le, double& lt, double& ld) {
+  le = lt = ld = 0;
   for (long q = p0; q < p0 + n; ++q) {
     int X, Y;
     tri_decode(q, X, Y);
@@ -79,7 +80,21 @@ inline void count_pairs(int v, long p0, long n, double& le, double& lt) {
     } else {
       le += nx * (nx + 1) / 2;
       lt += nx * (nx - 1) / 2;
+      ld += nx * (nx + 1) / 2;
     }
+  }
+}
+
+// The diagonal block pairs (Y, Y), at index Y (Y + 3) / 2, inside [p0, p0 + n): Y runs
+// over y0 .. y0 + count - 1.
+inline void diag_pairs(long p0, long n, int& y0, int& count) {
+  long y = 0;
+  while (y * (y + 3) / 2 < p0) ++y;
+  y0 = static_cast<int>(y);
+  count = 0;
+  while (y * (y + 3) / 2 < p0 + n) {
+    ++count;
+    ++y;
   }
 }
 
