@@ -51,6 +51,15 @@ def test_mfma_summary(tmp_path):
     assert abs(d["algorithmic_share"] - 2.56e10 / 5.12e10) < 1e-12
 
 
+def test_profiler_names_match_one_kernel_exactly():
+    from paper_1810_08142_amd.profiling import is_kernel
+    assert is_kernel("ri::ppl::build_w_f64(double const*, int)", "build_w_f64")
+    assert not is_kernel("ri::ppl::build_w_f64_diag(double const*, int)", "build_w_f64")
+    assert is_kernel("ri::ppl::build_w_f64_diag(double const*, int)", "build_w_f64_diag")
+    assert is_kernel("void ri::ppl::contract_f64<9>(double const*, long)", "contract_f64")
+    assert not is_kernel("void ri::ppl::contract_f64<9>(double const*, long)", "contract_f")
+
+
 def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
     assert r.returncode == 2
