@@ -13,10 +13,10 @@
 //                          the 8 consecutive Q a lane feeds to one MFMA
 //   Th/Tl [ij][slot]       packed tau+- (or tau-), slots contiguous
 //   Wh/Wl [ab slot][slot]  build output, already split, slots contiguous
-// Within a cd block pair the 256 slots are ordered so that the 8 (c, d) pairs one
-// wave of the build owns are consecutive: slot = quarter*64 + wave*8 + i*4 + j with
-// c = 8*(quarter>>1) + 2*(wave>>1) + i, d = 8*(quarter&1) + 4*(wave&1) + j.  A lane
-// then stores its 8 results for one (a, b) as one 16-byte run per array.
+// Within a cd block pair the 256 slots are ordered so that the 16 (c, d) pairs one
+// wave of the build owns are consecutive: slot = half*128 + wave*16 + i*4 + j with
+// c = 8*half + 4*(wave>>2) + i, d = 4*(wave&3) + j.  A lane then stores its 16 results
+// for one (a, b) as two 16-byte runs per array.
 //
 // MFMA v_mfma_f32_16x16x32_bf16 lane layout (measured): A[m][k] at lane m + 16*(k/8),
 // element k%8; B[k][n] at lane n + 16*(k/8), element k%8; D[m][n] at lane
@@ -82,9 +82,9 @@ __host__ __device__ inline int sw8(int m) { return (m ^ (m >> 3)) & 7; }
 
 // slot (0..255) of a cd block pair -> (c_in, d_in)
 __host__ __device__ inline void slot_cd(int slot, int& c_in, int& d_in) {
-  const int q = slot >> 6, w = (slot >> 3) & 7, i = (slot >> 2) & 1, j = slot & 3;
-  c_in = 8 * (q >> 1) + 2 * (w >> 1) + i;
-  d_in = 8 * (q & 1) + 4 * (w & 1) + j;
+  const int h = slot >> 7, w = (slot >> 4) & 7, i = (slot >> 2) & 3, j = slot & 3;
+  c_in = 8 * h + 4 * (w >> 2) + i;
+  d_in = 4 * (w & 3) + j;
 }
 
 // ---------------------------------------------------------------- split relayout
@@ -151,25 +151,31 @@ __global__ __launch_bounds__(256) void pack_tau_bf16_kernel(const double* __rest
 }
 
 // ---------------------------------------------------------------- build
-// Same decomposition as the FP64 build: one workgroup = ab block pair x one quarter
-// (8 c by 8 d) of a cd block pair; wave w owns c in {2(w>>1), +1}, d in {4(w&1)..+3}.
-// LDS per buffer: 16-byte runs [x 16][hl 2][e 32][run 4], run index XOR-swizzled with
-// sw4(e) so that the lanes of one ds_read_b128 hit distinct banks.
-// grid (nbp*4, slab_pairs), block 512
+// One workgroup = ab block pair x one half of a cd block pair: the 8 c of half h of
+// block Cb by all 16 d of block Db.  Eight waves; wave w owns c in 8h + 4(w>>2) + 0..3
+// and d in 4(w&3) + 0..3, so each fragment read from LDS feeds 12 MFMAs, and a Q step
+// stages 24 factor rows (8 c, 16 d) for 128 (c, d) pairs: 0.75 KB per pair and step.
+// LDS: a ring of three 48 KB slots.  A step occupies two slots (factor rows 0-11 in
+// the first, 12-23 in the second); while step s is computed, the first half of step
+// s + 1 is written into the third slot, and its second half into step s's first slot
+// once every wave has read it.  Each slot holds 16-byte runs [x 12][hl 2][e 32][run 4],
+// the run index XOR-swizzled with sw4(e) so that the lanes of one ds_read_b128 hit
+// distinct banks.
 // D: the workgroups of diagonal ab block pairs (Ab == Bb), blockIdx.y counting them
 // from block Ab = diag_y0; otherwise blockIdx.y is the slab's pair and diagonal pairs
 // exit at once.  In a diagonal pair the (ad|bc) tile is the transpose of the (ac|bd)
 // tile: only the latter is built, and the epilogue reads it back through LDS.
+// grid (nbp*2, slab_pairs or diagonal pairs), block 512
+constexpr int SLOT = 12 * 2 * 32 * 4;  // runs per LDS slot (48 KB)
 template <bool D>
 __device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
                                                   int Qp, int vp, long slab0, long K, int want_minus, int diag_y0,
                                                   uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
                                                   uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
-  constexpr int RUNS = 16 * 2 * 32 * 4;  // 4096 runs = 64 KB per buffer
-  __shared__ u32x4_t lds[2 * RUNS];
-  static_assert(2 * RUNS * 4 >= 8 * 8 * 256, "the staging buffer holds the transposed tiles");
-  const int quarter = blockIdx.x & 3;
-  const long pcd = blockIdx.x >> 2;
+  __shared__ u32x4_t lds[3 * SLOT];
+  static_assert(3 * SLOT * 4 >= 8 * 16 * 256, "the ring holds the transposed tiles");
+  const int half = blockIdx.x & 1;
+  const long pcd = blockIdx.x >> 1;
   int Cb, Db, Ab, Bb;
   tri_decode(pcd, Cb, Db);
   long pab_loc;
@@ -181,32 +187,50 @@ __device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ B
     tri_decode(slab0 + pab_loc, Ab, Bb);
     if (Ab == Bb) return;  // built by the diagonal launch (uniform over the workgroup)
   }
-  const int c_base = Cb * TB + (quarter >> 1) * 8;
-  const int d_base = Db * TB + (quarter & 1) * 8;
+  const int c_base = Cb * TB + half * 8;
+  const int d_base = Db * TB;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 
-  // staging: 8 runs per thread per step; every run of a thread comes from the same array
-  const int hl_t = (t >> 7) & 1;
-  const uint16_t* src = hl_t ? Bl : Bh;
-  size_t goff[8];
-  int loff[8];
+  // staging: run r (0..11) of a thread is run id = t + 512*r of the step, i.e. factor
+  // row x = 2r + (t >> 8) (x < 8: c rows, else d rows) with the thread's own
+  // (hl, e, run); runs 0-5 go to the step's first slot, 6-11 to its second.  The hi/lo
+  // array and the row parity are uniform over a wave, so the loads are buffer loads
+  // from two wave-uniform resources with one per-lane byte offset and a uniform offset
+  // per run and Q step.
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int hl_w = (wave >> 1) & 1, xt = wave >> 2, e_t = (t >> 2) & 31, run_t = t & 3;
+  const int ag = e_t < 16 ? Ab * TB + e_t : Bb * TB + (e_t - 16);
+  const uint16_t* src = hl_w ? Bl : Bh;
+  const size_t xs = static_cast<size_t>(vp) * Qp;  // elements from one factor row x to the next
+  const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint16_t*>(src + static_cast<size_t>(c_base + xt) * xs), 0, -1, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint16_t*>(src + static_cast<size_t>(d_base + xt) * xs), 0, -1, 0x00020000);
+  const int voff = (ag * Qp + run_t * 8) * 2;  // bytes
+  const int xsb2 = static_cast<int>(xs * 4);  // bytes for two factor rows
+  // LDS run of staging run r within its slot: x' = x mod 12 = 2(r mod 6) + xt
+  const int l0 = xt * 256 + (hl_w * 32 + e_t) * 4 + (run_t ^ sw4(e_t));  // + 512 per run
+  auto gload = [&](u32x4_t* dst, int h2, int step) {  // runs 6*h2 .. 6*h2 + 5
+    const int qb = step * QC * 2;  // bytes
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int id = t + 512 * r;
-    const int x = id >> 8, e = (id >> 2) & 31, run = id & 3;
-    const int cg = x < 8 ? c_base + x : d_base + (x - 8);
-    const int ag = e < 16 ? Ab * TB + e : Bb * TB + (e - 16);
-    goff[r] = (static_cast<size_t>(cg) * vp + ag) * Qp + run * 8;
-    loff[r] = ((x * 2 + hl_t) * 32 + e) * 4 + (run ^ sw4(e));
-  }
+    for (int k = 0; k < 6; ++k) {
+      const int r = 6 * h2 + k;
+      dst[k] = __builtin_bit_cast(u32x4_t, r < 4 ? __builtin_amdgcn_raw_buffer_load_b128(rc, voff, r * xsb2 + qb, 0)
+                                                 : __builtin_amdgcn_raw_buffer_load_b128(rd, voff, (r - 4) * xsb2 + qb, 0));
+    }
+  };
+  auto lstore = [&](const u32x4_t* sv, int slot) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) lds[slot * SLOT + l0 + 512 * k] = sv[k];
+  };
   // fragment addresses (run indices) for this lane
   const int fe = lane & 15, frun = lane >> 4;
   const int fsw = frun ^ sw4(fe);  // same swizzle for e and e + 16 (sw4 reads bits 1..3)
-  const int xc0 = (w >> 1) * 2, xd0 = 8 + (w & 1) * 4;
+  const int xc0 = (w >> 2) * 4, xd0 = 8 + (w & 3) * 4;
 
-  f32x4_t o1[2][4], o2[2][4];
+  f32x4_t o1[4][4], o2[4][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       o1[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -214,75 +238,81 @@ __device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ B
     }
 
   const int nsteps = Qp / QC;
-  // the c > d quarter of a diagonal cd block pair carries zero amplitudes: zeros only
-  const bool skip = Cb == Db && quarter == 2;
-  if (!skip) {
-    u32x4_t stage[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const u32x4_t*>(src + goff[r]);
-#pragma unroll
-    for (int r = 0; r < 8; ++r) lds[loff[r]] = stage[r];
-    __syncthreads();
-    for (int st = 0; st < nsteps; ++st) {
-      const int base = (st & 1) * RUNS;
-      const bool more = st + 1 < nsteps;
-      if (more) {
-        const size_t qo = static_cast<size_t>(st + 1) * QC;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) stage[r] = *reinterpret_cast<const u32x4_t*>(src + goff[r] + qo);
-      }
+  // in a diagonal cd block pair the slots with c > d carry zero amplitudes: a wave whose
+  // 4 x 4 pairs all have c > d skips its products (uniform over the wave)
+  const bool zero_w = Cb == Db && half == 1 && (w & 3) < 2;
+  {
+    // one Q step from the slots (s0: rows 0-11, s1: rows 12-23) into the accumulators
+    auto compute = [&](int s0, int s1) {
       auto frag = [&](int x, int hl, int e_off) -> bf16x8_t {
-        const u32x4_t v = lds[base + ((x * 2 + hl) * 32 + e_off + fe) * 4 + fsw];
+        const int base = x < 12 ? s0 * SLOT : s1 * SLOT;
+        const int xx = x < 12 ? x : x - 12;
+        const u32x4_t v = lds[base + ((xx * 2 + hl) * 32 + e_off + fe) * 4 + fsw];
         return __builtin_bit_cast(bf16x8_t, v);
       };
-      if constexpr (D) {
-        bf16x8_t ac[2][2];
+      {  // (ac|bd): c fragments of the a rows with d fragments of the b rows
+        bf16x8_t ac[4][2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int hl = 0; hl < 2; ++hl) ac[i][hl] = frag(xc0 + i, hl, 0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const bf16x8_t bdh = frag(xd0 + j, 0, 16), bdl = frag(xd0 + j, 1, 16);
 #pragma unroll
-          for (int i = 0; i < 2; ++i) o1[i][j] = mfma3(ac[i][0], ac[i][1], bdh, bdl, o1[i][j]);  // (ac|bd)
-        }
-      } else {
-      bf16x8_t ac[2][2], bc[2][2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int hl = 0; hl < 2; ++hl) {
-          ac[i][hl] = frag(xc0 + i, hl, 0);
-          bc[i][hl] = frag(xc0 + i, hl, 16);
-        }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bf16x8_t adh = frag(xd0 + j, 0, 0), adl = frag(xd0 + j, 1, 0);
-        const bf16x8_t bdh = frag(xd0 + j, 0, 16), bdl = frag(xd0 + j, 1, 16);
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          o1[i][j] = mfma3(ac[i][0], ac[i][1], bdh, bdl, o1[i][j]);  // (ac|bd)
-          o2[i][j] = mfma3_mirror(adh, adl, bc[i][0], bc[i][1], o2[i][j]);  // (ad|bc)
+          for (int i = 0; i < 4; ++i) o1[i][j] = mfma3(ac[i][0], ac[i][1], bdh, bdl, o1[i][j]);
         }
       }
-      }  // diag
-      if (more) {
-        const int nb = ((st + 1) & 1) * RUNS;
+      if constexpr (!D) {  // (ad|bc): d fragments of the a rows with c fragments of the b rows
+        bf16x8_t bc[4][2];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) lds[nb + loff[r]] = stage[r];
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int hl = 0; hl < 2; ++hl) bc[i][hl] = frag(xc0 + i, hl, 16);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bf16x8_t adh = frag(xd0 + j, 0, 0), adl = frag(xd0 + j, 1, 0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) o2[i][j] = mfma3_mirror(adh, adl, bc[i][0], bc[i][1], o2[i][j]);
+        }
       }
-      __syncthreads();
+    };
+    u32x4_t sa[6], sb[6];  // first and second half of the next step
+    gload(sa, 0, 0);
+    gload(sb, 1, 0);
+    lstore(sa, 0);
+    lstore(sb, 1);
+    if (nsteps > 1) {
+      gload(sa, 0, 1);
+      gload(sb, 1, 1);
     }
-  }  // !skip
+    __syncthreads();
+    int s0 = 0;  // slot of the current step's first half; its second half is s0 + 1 mod 3
+    for (int st = 0; st < nsteps; ++st) {
+      const int s1 = s0 == 2 ? 0 : s0 + 1, sf = s1 == 2 ? 0 : s1 + 1;
+      const bool more = st + 1 < nsteps;
+      if (more) {
+        lstore(sa, sf);  // first half of step st + 1 into the free slot
+        if (st + 2 < nsteps) gload(sa, 0, st + 2);
+      }
+      if (!zero_w) compute(s0, s1);
+      __syncthreads();  // every wave has read slot s0
+      if (more) {
+        lstore(sb, s0);  // second half of step st + 1
+        if (st + 2 < nsteps) gload(sb, 1, st + 2);
+        __syncthreads();
+      }
+      s0 = sf;
+    }
+  }
 
   if constexpr (D) {
-    // (ad|bc)[a][b] = (ac|bd)[b][a]: each wave stores its eight (ac|bd) tiles in its own
-    // 8 KB of the (now idle) staging buffer, element (a, b) at a*16 + (b ^ a), and reads
-    // them back transposed
-    float* tw = reinterpret_cast<float*>(lds) + w * (8 * 256);
+    // (ad|bc)[a][b] = (ac|bd)[b][a]: each wave stores its sixteen (ac|bd) tiles in its
+    // own 16 KB of the ring, element (a, b) at a*16 + (b ^ a), and reads them back
+    // transposed (the loop ended with every wave past its last fragment read)
+    float* tw = reinterpret_cast<float*>(lds) + w * (16 * 256);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -292,7 +322,7 @@ __device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ B
         }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -302,41 +332,45 @@ __device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ B
         }
   }
 
-  // epilogue: lane holds (a_in = 4*(lane>>4) + r, b_in = lane&15) for the wave's 8 slots
-  const size_t slot0 = static_cast<size_t>(pcd) * 256 + quarter * 64 + w * 8;
+  // epilogue: lane holds (a_in = 4*(lane>>4) + r, b_in = lane&15) for the wave's 16
+  // slots, stored as two 16-byte runs per array
+  const size_t slot0 = static_cast<size_t>(pcd) * 256 + half * 128 + w * 16;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int a_in = 4 * (lane >> 4) + r, b_in = lane & 15;
     const size_t row = static_cast<size_t>(pab_loc) * 256 + a_in * 16 + b_in;
-    uint16_t ph[8], pl[8], mh[8], ml[8];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int hh = 0; hh < 2; ++hh) {
+      uint16_t ph[8], pl[8], mh[8], ml[8];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float v1 = o1[i][j][r], v2 = o2[i][j][r];
-        split_f32(v1 + v2, ph[i * 4 + j], pl[i * 4 + j]);
-        split_f32(v1 - v2, mh[i * 4 + j], ml[i * 4 + j]);
-      }
-    u32x4_t h, l;
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      h[k] = static_cast<uint32_t>(ph[2 * k]) | (static_cast<uint32_t>(ph[2 * k + 1]) << 16);
-      l[k] = static_cast<uint32_t>(pl[2 * k]) | (static_cast<uint32_t>(pl[2 * k + 1]) << 16);
-    }
-    *reinterpret_cast<u32x4_t*>(Wph + row * K + slot0) = h;
-    *reinterpret_cast<u32x4_t*>(Wpl + row * K + slot0) = l;
-    if (want_minus) {
+        for (int j = 0; j < 4; ++j) {
+          const float v1 = o1[2 * hh + i][j][r], v2 = o2[2 * hh + i][j][r];
+          split_f32(v1 + v2, ph[i * 4 + j], pl[i * 4 + j]);
+          split_f32(v1 - v2, mh[i * 4 + j], ml[i * 4 + j]);
+        }
+      u32x4_t h, l;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        h[k] = static_cast<uint32_t>(mh[2 * k]) | (static_cast<uint32_t>(mh[2 * k + 1]) << 16);
-        l[k] = static_cast<uint32_t>(ml[2 * k]) | (static_cast<uint32_t>(ml[2 * k + 1]) << 16);
+        h[k] = static_cast<uint32_t>(ph[2 * k]) | (static_cast<uint32_t>(ph[2 * k + 1]) << 16);
+        l[k] = static_cast<uint32_t>(pl[2 * k]) | (static_cast<uint32_t>(pl[2 * k + 1]) << 16);
       }
-      *reinterpret_cast<u32x4_t*>(Wmh + row * K + slot0) = h;
-      *reinterpret_cast<u32x4_t*>(Wml + row * K + slot0) = l;
+      const size_t at = row * K + slot0 + 8 * hh;
+      *reinterpret_cast<u32x4_t*>(Wph + at) = h;
+      *reinterpret_cast<u32x4_t*>(Wpl + at) = l;
+      if (want_minus) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          h[k] = static_cast<uint32_t>(mh[2 * k]) | (static_cast<uint32_t>(mh[2 * k + 1]) << 16);
+          l[k] = static_cast<uint32_t>(ml[2 * k]) | (static_cast<uint32_t>(ml[2 * k + 1]) << 16);
+        }
+        *reinterpret_cast<u32x4_t*>(Wmh + at) = h;
+        *reinterpret_cast<u32x4_t*>(Wml + at) = l;
+      }
     }
   }
 }
-
 __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
                                                       int Qp, int vp, long slab0, long K, int want_minus,
                                                       uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
@@ -509,6 +543,9 @@ static bool make_mplan(int o, int v, int naux, MPlan& p) {
   p.nb = (v + TB - 1) / TB;
   p.vp = p.nb * TB;
   p.Qp = static_cast<int>(round_up(naux, QC));
+  // the build's buffer loads reach eight factor rows of vp * Qp bf16 words past their
+  // base with 32-bit byte offsets
+  if (static_cast<double>(p.vp) * p.Qp * 2 * 8 >= 2147483648.0) return false;
   p.nbp = static_cast<long>(p.nb) * (p.nb + 1) / 2;
   p.K = p.nbp * 256;
   p.po = o * (o + 1) / 2;
@@ -631,13 +668,13 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
       const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, p.K, kzm) : 1;
       {  // off-diagonal and diagonal ab block pairs in two launches
         ProfScope ps(s, "build_w_bf16x3", 2.0 * naux * vv * (le - ld));
-        build_w_bf16x3<<<dim3(p.nbp * 4, npairs), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K, p.pm > 0 ? 1 : 0,
+        build_w_bf16x3<<<dim3(p.nbp * 2, npairs), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K, p.pm > 0 ? 1 : 0,
                                                               Wph, Wpl, Wmh, Wml);
         if ((rc = check_launch("build_w_bf16x3"))) break;
       }
       if (ndiag > 0) {
         ProfScope ps(s, "build_w_bf16x3_diag", 2.0 * naux * vv * ld);
-        build_w_bf16x3_diag<<<dim3(p.nbp * 4, ndiag), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K,
+        build_w_bf16x3_diag<<<dim3(p.nbp * 2, ndiag), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K,
                                                                    p.pm > 0 ? 1 : 0, dy0, Wph, Wpl, Wmh, Wml);
         if ((rc = check_launch("build_w_bf16x3_diag"))) break;
       }
