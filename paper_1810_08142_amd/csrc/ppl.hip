@@ -39,6 +39,7 @@ namespace ri {
 namespace ppl {
 
 constexpr int KC = 16;  // auxiliary functions (build) or cd slots (contraction) per LDS step
+constexpr int CRM = 128;  // contraction tile rows (four waves of CRM / 4)
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef double double2_t __attribute__((ext_vector_type(2)));  // register-promotable (unlike double2)
@@ -337,10 +338,12 @@ __global__ __launch_bounds__(512) void build_w_f32_diag(const float* __restrict_
 }
 
 // ---------------------------------------------------------------- 3b. contract
-// C[m][n] = sum_k W[k][m] T[k][n];  tile 64 (m) x 16*NTW (n); 4 waves, wave w owns
-// rows 16w..16w+15 and all columns.  The k range may be split over grid.z: split z
-// sums k in [z*kz, min(K, (z+1)*kz)) into C + z*zs, and the unpack adds the splits in
-// order.  grid (ncol/(16*NTW), M/64, splits), block 256
+// C[m][n] = sum_k W[k][m] T[k][n];  tile CRM (m) x 16*NTW (n); 4 waves, wave w owns
+// rows w*CRM/4 .. (w+1)*CRM/4 - 1 (CRM/64 MFMA row tiles, each B fragment feeds all of
+// them) and all columns.  Every row tile streams the whole packed tau, so taller tiles
+// read it fewer times.  The k range may be split over grid.z: split z sums k in
+// [z*kz, min(K, (z+1)*kz)) into C + z*zs, and the unpack adds the splits in order.
+// grid (ncol/(16*NTW), M/CRM, splits), block 256
 template <class T, int NTW>
 __device__ __forceinline__ void contract_body(const T* __restrict__ W, const T* __restrict__ Tt, long K, long M,
                                               int ncol, T* __restrict__ C, long kz, long zs) {
@@ -348,38 +351,39 @@ __device__ __forceinline__ void contract_body(const T* __restrict__ W, const T* 
   typedef Mfma<T> MF;
   typedef typename MF::vec_t vec_t;
   constexpr int BN = 16 * NTW;
+  constexpr int RW = CRM / 64;                  // 16-row MFMA tiles per wave
   constexpr int VEC = 16 / sizeof(T);
-  constexpr int AV = 64 / VEC;                  // loads per k row of the A tile
-  constexpr int NA = KC * 64 / (256 * VEC);     // A loads per thread per chunk
-  __shared__ T sA[2][KC][64];
+  constexpr int AV = CRM / VEC;                 // loads per k row of the A tile
+  constexpr int NA = KC * CRM / (256 * VEC);    // A loads per thread per chunk
+  __shared__ T sA[2][KC][CRM];
   __shared__ T sB[2][KC][BN];
   unsigned tx, ty;
   xcd_tile(tx, ty);
-  const long n0 = static_cast<long>(tx) * BN, m0 = static_cast<long>(ty) * 64;
+  const long n0 = static_cast<long>(tx) * BN, m0 = static_cast<long>(ty) * CRM;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   {  // this split's k range (every split holds at least one chunk)
     const long k_lo = blockIdx.z * kz;
     K = (K < k_lo + kz ? K : k_lo + kz) - k_lo;
-    W += k_lo * M;
-    Tt += k_lo * ncol;
+    W += k_lo * M + m0;
+    Tt += k_lo * ncol + n0;
     C += blockIdx.z * zs;
   }
 
-  // staging offsets (computed once; the chunk loop adds k0 * row stride)
-  long aoff[NA], boff[NTW];
+  // staging offsets within a chunk (the chunk loop advances the base pointers)
+  int aoff[NA], boff[NTW];
   int alo[NA], blo[NTW];
 #pragma unroll
   for (int r = 0; r < NA; ++r) {
     const int p2 = t + 256 * r;
     const int k = p2 / AV, mm = (p2 % AV) * VEC;
-    aoff[r] = k * M + m0 + mm;
-    alo[r] = k * 64 + mm;
+    aoff[r] = k * static_cast<int>(M) + mm;
+    alo[r] = k * CRM + mm;
   }
 #pragma unroll
   for (int r = 0; r < NTW; ++r) {
     const int e = t + 256 * r;
     const int k = e / BN, nn = e % BN;
-    boff[r] = static_cast<long>(k) * ncol + n0 + nn;
+    boff[r] = k * ncol + nn;
     blo[r] = k * BN + nn;
   }
   vec_t ra[NA];
@@ -387,9 +391,11 @@ __device__ __forceinline__ void contract_body(const T* __restrict__ W, const T* 
   T* sA0 = &sA[0][0][0];
   T* sB0 = &sB[0][0][0];
 
-  typename MF::acc_t acc[NTW];
+  typename MF::acc_t acc[RW][NTW];
 #pragma unroll
-  for (int u = 0; u < NTW; ++u) acc[u] = MF::zero();
+  for (int q = 0; q < RW; ++q)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) acc[q][u] = MF::zero();
   const int m = lane & 15, kq = lane >> 4;
   const long nchunks = K / KC;
 #pragma unroll
@@ -405,34 +411,43 @@ __device__ __forceinline__ void contract_body(const T* __restrict__ W, const T* 
     const int buf = ch & 1;
     const bool more = ch + 1 < nchunks;
     if (more) {
-      const long k0 = (ch + 1) * KC;
+      const T* Wc = W + (ch + 1) * KC * M;
+      const T* Tc = Tt + (ch + 1) * KC * ncol;
 #pragma unroll
-      for (int r = 0; r < NA; ++r) ra[r] = *reinterpret_cast<const vec_t*>(W + aoff[r] + k0 * M);
+      for (int r = 0; r < NA; ++r) ra[r] = *reinterpret_cast<const vec_t*>(Wc + aoff[r]);
 #pragma unroll
-      for (int r = 0; r < NTW; ++r) rb[r] = Tt[boff[r] + k0 * ncol];
+      for (int r = 0; r < NTW; ++r) rb[r] = Tc[boff[r]];
     }
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int kk = 4 * s + kq;
-      const T a = sA[buf][kk][w * 16 + m];
+      T a[RW];
 #pragma unroll
-      for (int u = 0; u < NTW; ++u) acc[u] = MF::mma(a, sB[buf][kk][u * 16 + m], acc[u]);
+      for (int q = 0; q < RW; ++q) a[q] = sA[buf][kk][(w * RW + q) * 16 + m];
+#pragma unroll
+      for (int u = 0; u < NTW; ++u) {
+        const T b = sB[buf][kk][u * 16 + m];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) acc[q][u] = MF::mma(a[q], b, acc[q][u]);
+      }
     }
     if (more) {
 #pragma unroll
-      for (int r = 0; r < NA; ++r) *reinterpret_cast<vec_t*>(sA0 + (buf ^ 1) * KC * 64 + alo[r]) = ra[r];
+      for (int r = 0; r < NA; ++r) *reinterpret_cast<vec_t*>(sA0 + (buf ^ 1) * KC * CRM + alo[r]) = ra[r];
 #pragma unroll
       for (int r = 0; r < NTW; ++r) sB0[(buf ^ 1) * KC * BN + blo[r]] = rb[r];
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < NTW; ++u)
+  for (int q = 0; q < RW; ++q)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long row = m0 + w * 16 + MF::drow(r, lane);
-      C[row * ncol + n0 + u * 16 + m] = acc[u][r];
-    }
+    for (int u = 0; u < NTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long row = m0 + (w * RW + q) * 16 + MF::drow(r, lane);
+        C[row * ncol + n0 + u * 16 + m] = acc[q][u][r];
+      }
 }
 template <int NTW>
 __global__ __launch_bounds__(256) void contract_f64(const double* __restrict__ W, const double* __restrict__ Tt,
@@ -544,7 +559,7 @@ struct Plan {
 // column tiles: enough workgroups to fill the chip about three deep (the kernel's
 // occupancy), at least 32 chunks per split.  kz: summed indices per split.
 static int contract_splits(int ncol, int ntw, long rows, long K, long& kz) {
-  const long nwg = (ncol / (16 * ntw)) * (rows / 64);
+  const long nwg = (ncol / (16 * ntw)) * (rows / CRM);
   long z = (3 * 256 + nwg - 1) / nwg;
   z = std::max(1L, std::min(z, K / (32 * KC)));
   kz = (K + z - 1) / z;
@@ -576,8 +591,8 @@ static bool make_plan(int o, int v, int naux, size_t esize, Plan& p) {
   p.K = p.nbp * 256;
   p.po = o * (o + 1) / 2;
   p.pm = o * (o - 1) / 2;
-  pick_ntw(p.po, 10, 64, p.ntw_p, p.NP);
-  pick_ntw(p.pm, 10, 64, p.ntw_m, p.NM);
+  pick_ntw(p.po, 10, CRM, p.ntw_p, p.NP);
+  pick_ntw(p.pm, 10, CRM, p.ntw_m, p.NM);
   if (p.pm == 0) p.NM = 0;
   const int nw = p.pm > 0 ? 2 : 1;
   const long budget = env_long("RI_PPL_W_BYTES", 16L << 30);
@@ -661,12 +676,12 @@ struct K32 {
   }
 };
 
-// rows: number of C rows (multiple of 64) computed; ldw: row stride of W.  The k
+// rows: number of C rows (multiple of CRM) computed; ldw: row stride of W.  The k
 // range is split `splits` ways (kz each) into partial outputs rows*ncol apart.
 template <class KS>
 static void launch_contract(int ntw, const typename KS::T* W, const typename KS::T* Tt, long K, long ldw, long rows,
                             int ncol, typename KS::T* C, int splits, long kz, hipStream_t s) {
-  const unsigned gy = static_cast<unsigned>(rows / 64), gz = static_cast<unsigned>(splits);
+  const unsigned gy = static_cast<unsigned>(rows / CRM), gz = static_cast<unsigned>(splits);
   const long zs = rows * ncol;
   switch (ntw) {
     case 1: KS::template contract_k<1>(dim3(ncol / 16, gy, gz), s, W, Tt, K, ldw, ncol, C, kz, zs); break;
