@@ -386,11 +386,11 @@ __global__ __launch_bounds__(512) void build_w_bf16x3_diag(const uint16_t* __res
 }
 
 // ---------------------------------------------------------------- contract
-// C[m][n] = sum_k W[m][k] T[n][k] (both split); tile 128 (m) x 16*NTW (n); four waves,
-// wave w owns rows 32w..32w+31 (two m tiles) and all columns.  LDS holds 16-byte runs
-// [row][8 runs: hl 2 x run 4], run index XOR-swizzled with sw8(row).  The k range may
-// be split over grid.z: split z sums k in [z*kz, min(K, (z+1)*kz)) into C + z*zs.
-// grid (ncol/(16*NTW), rows/128, splits), block 256
+// C[m][n] = sum_k W[m][k] T[n][k] (both split); tile CBM (m) x 16*NTW (n); CBM/32
+// waves, wave w owns rows 32w..32w+31 (two m tiles) and all columns.  LDS holds 16-byte
+// runs [row][8 runs: hl 2 x run 4], run index XOR-swizzled with sw8(row).  The k range
+// may be split over grid.z: split z sums k in [z*kz, min(K, (z+1)*kz)) into C + z*zs.
+// grid (ncol/(16*NTW), rows/CBM, splits), block CNT
 template <int NTW>
 __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
                                                        const uint16_t* __restrict__ Th, const uint16_t* __restrict__ Tl,
