@@ -64,9 +64,10 @@ __device__ inline f32x4_t mfma3(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t 
   c = mfma_bf16(al, bh, c);
   return mfma_bf16(ah, bh, c);
 }
-// The same with the two cross terms in the mirrored order.  Used for (ad|bc) so that
-// at a == b it accumulates exactly the products of (ac|bd) in the same order: the
-// difference V- = (ac|bd) - (ad|bc) is then exactly zero there, as in exact arithmetic.
+// The same with the two cross terms in the mirrored order, used for (ad|bc): (ad|bc)
+// for (a, b) then accumulates the products of (ac|bd) for (b, a) in the same order.
+// (a == b occurs only in diagonal ab block pairs, whose (ad|bc) tile is read back as
+// the transpose of the (ac|bd) tile, so V- = (ac|bd) - (ad|bc) is exactly zero there.)
 __device__ inline f32x4_t mfma3_mirror(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t bl, f32x4_t c) {
   c = mfma_bf16(al, bh, c);
   c = mfma_bf16(ah, bl, c);
