@@ -82,7 +82,9 @@ int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double
  * bf16 hi + lo pair), rebuild the integrals with FP32 accumulation, round them
  * again for the contraction and add the FP32 result into the FP64 R; the error of
  * an element is bounded by 2e-4 times the ladder of |B_vv| and |tau| (and is a few
- * 1e-6 of max |R| for bf16 hi + lo, less for FP32). */
+ * 1e-6 of max |R| for bf16 hi + lo, less for FP32).  RI_PREC_BF16X3 needs
+ * vp * Qp < 2^27 (vp = v rounded up to 16, Qp = naux rounded up to 32), RI_E_ARG
+ * otherwise. */
 int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
               int precision, void* ws, size_t ws_bytes, void* stream);
 

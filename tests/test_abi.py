@@ -50,6 +50,9 @@ def test_argument_checks_before_any_device_work():
     assert L.ri_ppl_workspace_bytes(2, 20, 8, 0) > 0
     # overlapping output and input
     assert L.ri_ppl(4096, 8192, 2, 3, 4, 8192, None) == 2
+    # the split path's size limit: vp * Qp < 2^27
+    assert L.ri_ppl_workspace_bytes(2, 8192, 16384, 2) == 0
+    assert L.ri_ppl_workspace_bytes(2, 4096, 16384, 2) > 0
 
 
 def test_mlp_training_options_and_checks():
