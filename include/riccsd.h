@@ -101,6 +101,19 @@ int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, dou
 int ri_ppl_shard(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
                  int precision, int shard, int nshards, void* ws, size_t ws_bytes, void* stream);
 
+/* The same ladder in the paper's own arrangement (Sec. II.C, Fig. 2), FP64, kept as
+ * an ablation of the tau+- form: for every virtual a the full (ac|bd) slice over
+ * (b, c, d) is built from B_vv and contracted with tau over the packed occupied pairs
+ * i <= j only; the i > j entries follow from R^{ab}_{ij} = R^{ba}_{ji}.  Arguments,
+ * layouts, accumulation, the use of tau's pair-symmetric part and the error codes are
+ * those of ri_ppl; the result agrees with ri_ppl to rounding.  Cost (ri_ppl_paper_flops):
+ * 2 Naux v^4 + v^4 o(o+1) FLOP, about twice the build and four times the contraction of
+ * ri_ppl.  Device workspace of 2 v^2 o(o+1)/2 + a v^3 doubles (a = the values of the
+ * first virtual index per step, within RI_PPL_PAPER_V_BYTES, 4 GiB by default) is
+ * taken stream-ordered for the call. */
+int ri_ppl_paper(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream);
+double ri_ppl_paper_flops(int o, int v, int naux);
+
 /* Workspace bytes ri_ppl_ex needs for these sizes (0 on invalid arguments). */
 size_t ri_ppl_workspace_bytes(int o, int v, int naux, int precision);
 

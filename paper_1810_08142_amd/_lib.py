@@ -59,6 +59,8 @@ _SIGS = [
     ("ri_ppl_ex", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _c.c_int, _dp, _c.c_size_t, _dp]),
     ("ri_ppl_shard", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _c.c_int, _c.c_int, _c.c_int, _dp,
                                 _c.c_size_t, _dp]),
+    ("ri_ppl_paper", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _dp]),
+    ("ri_ppl_paper_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_workspace_bytes", _c.c_size_t, [_c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_build_tau", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _dp, _dp]),

@@ -4,6 +4,7 @@
                                         [--polish 1e-6] [--check-fp64] [--model net.bin]
   python -m paper_1810_08142_amd.cli ttc --config c3 --scale naux [--polish 1e-6]
   python -m paper_1810_08142_amd.cli shard --config c4 --nshards 8 [--precision fp64|fp32|bf16x3]
+  python -m paper_1810_08142_amd.cli ablation --config c2
 
 `ccsd` prints one JSON line with the report (energy, iterations, timings, scale
 used).  `ttc` (time to converged E_corr) solves one system four times -- FP64
@@ -12,7 +13,10 @@ and prints one JSON line per run with its E_corr error against the FP64 run and 
 FP64 residual of its final amplitudes.  `shard` times every shard k of n of one ladder call (ri_ppl_shard, the
 per-device work of an n-device split over the (ab) slabs) one after another and prints
 the slowest and mean shard, with the R bytes one device would contribute to the
-all-gather that completes the call.
+all-gather that completes the call.  `ablation` times one ladder call in the paper's
+arrangement (ri_ppl_paper: full (a, b) build, i <= j pairs) against the tau+- form
+(ri_ppl, FP64) on the same inputs, with each one's own FLOP count and the largest
+difference between the two results.
 """
 from __future__ import annotations
 
@@ -49,6 +53,9 @@ def main(argv=None):
     t.add_argument("--tol", type=float, default=1e-8)
     t.add_argument("--tol-energy", type=float, default=1e-9)
     t.add_argument("--verbose", action="store_true")
+    ab = sub.add_parser("ablation")
+    ab.add_argument("--config", default="c2")
+    ab.add_argument("--repeat", type=int, default=2)
     sh = sub.add_parser("shard")
     sh.add_argument("--config", default="c4")
     sh.add_argument("--nshards", type=int, default=8)
@@ -58,6 +65,8 @@ def main(argv=None):
         return _ttc(args)
     if args.cmd == "shard":
         return _shard(args)
+    if args.cmd == "ablation":
+        return _ablation(args)
 
     import torch
 
@@ -125,6 +134,57 @@ def _ttc(args):
         print(json.dumps(out), flush=True)
         rc = rc or (0 if rep.converged else 3)
     return rc
+
+
+def _inputs(config):
+    """B_vv and tau = MP2 t2 + t1 t1 of a ladder workload, on the device."""
+    import torch
+
+    from . import ccsd, ppl
+    from .synthetic import CONFIGS, draw_system
+    cfg = CONFIGS[config]
+    s = draw_system(cfg["o"], cfg["v"], cfg["naux"], seed=cfg["seed"])
+    o = s.o
+    B = torch.from_numpy(s.B).to("cuda")
+    eps = torch.from_numpy(s.eps).to("cuda")
+    t1 = torch.from_numpy(s.t1).to("cuda")
+    t2, _ = ccsd.mp2_guess(B, eps, o)
+    tau = ppl.build_tau(t1, t2)
+    B_vv = B[:, o:, o:].contiguous()
+    return s.o, s.v, s.naux, B_vv, tau
+
+
+def _ablation(args):
+    import torch
+
+    from . import ppl
+    o, v, naux, B_vv, tau = _inputs(args.config)
+    out = dict(config=args.config, o=o, v=v, naux=naux)
+    res = {}
+    for name, call, fl in (("tau_pm", lambda R: ppl.ppl(B_vv, tau, R), ppl.flops(o, v, naux)),
+                           ("paper", lambda R: ppl.ppl_paper(B_vv, tau, R), ppl.paper_flops(o, v, naux))):
+        R = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+        call(R)  # warm-up (and the result compared below)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(args.repeat):
+            Rt = torch.zeros_like(R)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            call(Rt)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+            del Rt
+        res[name] = R
+        out[name] = dict(ms=best, flop=fl, tflops=fl / (best * 1e-3) / 1e12)
+        print(json.dumps({name: out[name]}), file=sys.stderr, flush=True)
+    d = (res["paper"] - res["tau_pm"]).abs().max().item()
+    out["max_abs_diff_rel"] = d / res["tau_pm"].abs().max().item()
+    out["paper_over_tau_pm_time"] = out["paper"]["ms"] / out["tau_pm"]["ms"]
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def _shard(args):

@@ -59,6 +59,24 @@ def ppl(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, precision="fp64"
     return R
 
 
+def ppl_paper(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, stream=None) -> torch.Tensor:
+    """The same sum in the paper's arrangement (full (a, b) build, i <= j pairs only;
+    ri_ppl_paper), FP64: the ablation of the tau+- form."""
+    naux, v = B_vv.shape[0], B_vv.shape[1]
+    o = tau.shape[0]
+    _need(B_vv, "B_vv", (naux, v, v))
+    _need(tau, "tau", (o, o, v, v))
+    _need(R, "R", (o, o, v, v))
+    _lib.check(_lib.lib().ri_ppl_paper(B_vv.data_ptr(), tau.data_ptr(), o, v, naux, R.data_ptr(), _stream(stream)),
+               "ri_ppl_paper")
+    return R
+
+
+def paper_flops(o: int, v: int, naux: int) -> float:
+    """FLOP of ri_ppl_paper: 2 Naux v^4 (full build) + v^4 o(o+1) (i <= j contraction)."""
+    return float(_lib.lib().ri_ppl_paper_flops(o, v, naux))
+
+
 def workspace_bytes(o: int, v: int, naux: int, precision="fp64") -> int:
     return int(_lib.lib().ri_ppl_workspace_bytes(o, v, naux, _prec(precision)))
 

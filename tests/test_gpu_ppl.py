@@ -264,3 +264,66 @@ def test_pair_asymmetry_measure_and_debug_check(monkeypatch):
     monkeypatch.setenv("RI_PPL_CHECK_TAU", "0")
     ppl.ppl(B, dev(bad), R)  # check off: the symmetric part is used
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("o,v,naux", [(1, 3, 2), (2, 17, 7), (3, 33, 20), (4, 40, 37), (2, 50, 130)])
+def test_paper_arrangement_matches_oracle_and_tau_pm(o, v, naux):
+    """ri_ppl_paper (full (a, b) build, i <= j pairs) gives the oracle's ladder to 1e-11
+    and ri_ppl's to rounding; entries with i < j and their mirrors are bitwise equal."""
+    import torch
+    ppl = _ppl()
+    s = draw_system(o, v, naux, seed=o * 100 + v)
+    T = draw_pair_symmetric(o, v, 7 + v, 0.01)
+    R0 = draw_matrix((o, o, v, v), 3)
+    ref = native.ppl(np.ascontiguousarray(s.B_vv), T, R0.copy())
+    R = dev(R0)
+    ppl.ppl_paper(dev(np.ascontiguousarray(s.B_vv)), dev(T), R)
+    got = host(R)
+    assert rel_max(got - R0, ref - R0) <= TOL and rel_fro(got - R0, ref - R0) <= TOL
+    Rt = _gpu_ladder(s.B_vv, T, R0)
+    assert rel_max(got - R0, Rt - R0) <= TOL
+    Z = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    ppl.ppl_paper(dev(np.ascontiguousarray(s.B_vv)), dev(T), Z)
+    add = host(Z)
+    for i in range(o):
+        for j in range(i + 1, o):
+            assert np.array_equal(add[i, j], add[j, i].T)
+
+
+def test_paper_arrangement_pair_symmetrises_tau_and_checks_arguments():
+    import torch
+    from paper_1810_08142_amd import _lib
+    ppl = _ppl()
+    o, v, naux = 3, 21, 11
+    s = draw_system(o, v, naux, seed=4)
+    T = draw_matrix((o, o, v, v), 9)  # not pair-symmetric
+    Ts = 0.5 * (T + T.transpose(1, 0, 3, 2))
+    B = dev(np.ascontiguousarray(s.B_vv))
+    R1 = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    R2 = torch.zeros_like(R1)
+    ppl.ppl_paper(B, dev(T), R1)
+    ppl.ppl_paper(B, dev(Ts), R2)
+    assert rel_max(host(R1), host(R2)) <= 1e-13
+    assert ppl.paper_flops(o, v, naux) == 2.0 * naux * v**4 + v**4 * o * (o + 1)
+    L = _lib.lib()
+    assert L.ri_ppl_paper(None, B.data_ptr(), o, v, naux, R1.data_ptr(), None) == 1
+    assert L.ri_ppl_paper(B.data_ptr(), B.data_ptr(), o, v, naux, B.data_ptr(), None) == 2
+    torch.cuda.synchronize()
+
+
+def test_paper_arrangement_chunks_do_not_change_result(monkeypatch):
+    """The chunk of a values per build step (RI_PPL_PAPER_V_BYTES: 1, 7 with a ragged
+    last chunk, all 40) changes the result only by rounding."""
+    import torch
+    ppl = _ppl()
+    o, v, naux = 2, 40, 24
+    s = draw_system(o, v, naux, seed=6)
+    T = dev(draw_pair_symmetric(o, v, 5, 0.01))
+    B = dev(np.ascontiguousarray(s.B_vv))
+    outs = []
+    for vb in (v**3 * 8, 7 * v**3 * 8, 1 << 30):
+        monkeypatch.setenv("RI_PPL_PAPER_V_BYTES", str(vb))
+        R = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+        ppl.ppl_paper(B, T, R)
+        outs.append(host(R))
+    assert rel_max(outs[1], outs[0]) <= 1e-13 and rel_max(outs[2], outs[0]) <= 1e-13
