@@ -360,3 +360,41 @@ def fci_two_electron(B: np.ndarray, eps: np.ndarray) -> float:
     ref[0] = 1.0                                     # (p, q) = (0, 0)
     k = int(np.argmax(np.abs(vecs.T @ ref)))
     return float(w[k] - e_ref)
+
+
+def triples(B: np.ndarray, eps: np.ndarray, o: int, t1: np.ndarray, t2: np.ndarray) -> float:
+    """Perturbative triples energy E_(T) of the closed-shell formula of Sec. II.A:
+
+        E_(T) = sum_{ijk} sum_{abc} (4 W^{abc}_{ijk} + W^{bca}_{ijk} + W^{cab}_{ijk})
+                                     (V^{abc}_{ijk} - V^{cba}_{ijk}) / (3 D^{abc}_{ijk}),
+        W^{abc}_{ijk} = P^{abc}_{ijk} ( sum_d v^{ba}_{di} t^{cd}_{kj} - sum_l v^{cj}_{kl} t^{ab}_{il} ),
+        V^{abc}_{ijk} = W^{abc}_{ijk} + v^{bc}_{jk} t^a_i + v^{ac}_{ik} t^b_j + v^{ab}_{ij} t^c_k,
+        D^{abc}_{ijk} = e_i + e_j + e_k - e_a - e_b - e_c,
+
+    with v^{pq}_{rs} = (pr|qs) and P^{abc}_{ijk} the sum over the six simultaneous
+    permutations of the column pairs (i, a), (j, b), (k, c).  Full o^3 v^3 arrays:
+    for small systems only."""
+    v = t1.shape[1]
+    g = eri(B, B)
+    O, V = slice(0, o), slice(o, o + v)
+    g_vvvo = g[V, V, V, O]  # (bd|ai) at [b][d][a][i]
+    g_vooo = g[V, O, O, O]  # (ck|jl) at [c][k][j][l]
+    g_ovov = g[O, V, O, V]  # (ia|jb) at [i][a][j][b]
+    # X(ijk, abc) = sum_d v^{ba}_{di} t^{cd}_{kj} - sum_l v^{cj}_{kl} t^{ab}_{il}
+    #             = sum_d (bd|ai) t2[k,j,c,d]   - sum_l (ck|jl) t2[i,l,a,b]
+    X = (np.einsum("bdai,kjcd->ijkabc", g_vvvo, t2, **_es)
+         - np.einsum("ckjl,ilab->ijkabc", g_vooo, t2, **_es))
+    # P: f(ijk,abc) + f(ikj,acb) + f(kij,cab) + f(kji,cba) + f(jki,bca) + f(jik,bac)
+    W = (X + np.einsum("ikjacb->ijkabc", X) + np.einsum("kijcab->ijkabc", X)
+         + np.einsum("kjicba->ijkabc", X) + np.einsum("jkibca->ijkabc", X) + np.einsum("jikbac->ijkabc", X))
+    # v^{bc}_{jk} = (bj|ck) = (jb|kc)
+    Vt = (W + np.einsum("jbkc,ia->ijkabc", g_ovov, t1) + np.einsum("iakc,jb->ijkabc", g_ovov, t1)
+          + np.einsum("iajb,kc->ijkabc", g_ovov, t1))
+    e_o, e_v = eps[:o], eps[o:]
+    D = (e_o[:, None, None, None, None, None] + e_o[None, :, None, None, None, None]
+         + e_o[None, None, :, None, None, None] - e_v[None, None, None, :, None, None]
+         - e_v[None, None, None, None, :, None] - e_v[None, None, None, None, None, :])
+    W_bca = np.einsum("ijkbca->ijkabc", W)  # W^{bca}_{ijk} as an array over (a, b, c)
+    W_cab = np.einsum("ijkcab->ijkabc", W)
+    V_cba = np.einsum("ijkcba->ijkabc", Vt)
+    return float(np.sum((4.0 * W + W_bca + W_cab) * (Vt - V_cba) / (3.0 * D)))

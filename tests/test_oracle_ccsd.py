@@ -138,3 +138,53 @@ def test_dressing_is_similarity_transform():
     s = draw_system(o, v, 3, seed=161)
     back = oc.dress(oc.dress(s.B, t1), -t1)
     np.testing.assert_allclose(back, s.B, atol=1e-15)
+
+
+def _triples_det_space(ds, h, g, eps, t1, t2):
+    """E_(T) as the perturbative functional on the triply excited determinants T:
+    sum_T x_T (x_T + y_T) / D_T with x = <T|H T2|0>, y = <T|H T1|0> and D_T the sum of
+    the orbital energies of the vacated minus the filled spin orbitals (with a Fock
+    matrix diag(eps) the one-electron part cannot reach T from singles or doubles)."""
+    o, v = t1.shape
+    ref = ds.reference()
+    x = ds.apply_H(h, g, ds.apply_T(np.zeros_like(t1), t2, ref))
+    y = ds.apply_H(h, g, ds.apply_T(t1, np.zeros_like(t2), ref))
+    occ = (1 << o) - 1
+    m = len(ds.strs)
+    e = 0.0
+    for ka, sa in enumerate(ds.strs):
+        for kb, sb in enumerate(ds.strs):
+            holes = [p for p in range(o) if not (sa >> p) & 1] + [p for p in range(o) if not (sb >> p) & 1]
+            parts = [p for p in range(o, o + v) if (sa >> p) & 1] + [p for p in range(o, o + v) if (sb >> p) & 1]
+            if len(holes) != 3:
+                continue
+            k = ka * m + kb
+            d = sum(eps[p] for p in holes) - sum(eps[p] for p in parts)
+            e += x[k] * (x[k] + y[k]) / d
+    return e
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(2, 3, 6, 200), (2, 4, 8, 201), (3, 4, 9, 202), (3, 5, 10, 203)])
+def test_triples_energy_equals_determinant_space_functional(o, v, naux, seed):
+    """The closed-shell (T) formula of Sec. II.A equals the (T) functional evaluated
+    on explicit triply excited determinants, at arbitrary pair-symmetric amplitudes;
+    both of its parts (through t2 alone and through t1) are far above the tolerance."""
+    s, h, e_ref, g = _setup(o, v, naux, seed)
+    t1 = draw_matrix((o, v), seed + 1, 0.1)
+    t2 = draw_pair_symmetric(o, v, seed + 2, 0.1)
+    ds = DetSpace(o + v, o)
+    ref = _triples_det_space(ds, h, g, s.eps, t1, t2)
+    got = oc.triples(s.B, s.eps, o, t1, t2)
+    only_t2 = oc.triples(s.B, s.eps, o, np.zeros_like(t1), t2)
+    assert abs(only_t2) > 1e-3 and abs(got - only_t2) > 1e-4
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref))
+    assert abs(only_t2 - _triples_det_space(ds, h, g, s.eps, np.zeros_like(t1), t2)) <= 1e-12
+
+
+@pytest.mark.parametrize("v,seed", [(4, 300), (9, 301)])
+def test_triples_vanish_for_two_electrons(v, seed):
+    """With one occupied orbital there are no triple excitations: E_(T) = 0."""
+    s = draw_system(1, v, 2 * v, seed=seed, scale=0.3)
+    t1 = draw_matrix((1, v), seed + 1, 0.2)
+    t2 = draw_pair_symmetric(1, v, seed + 2, 0.2)
+    assert abs(oc.triples(s.B, s.eps, 1, t1, t2)) <= 1e-14
