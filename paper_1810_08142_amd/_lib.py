@@ -72,6 +72,8 @@ _SIGS = [
     ("ri_ccsd_energy", _c.c_int, [_sysp, _dp, _dp, _dblp, _dp]),
     ("ri_ccsd_residual", _c.c_int, [_sysp, _dp, _dp, _dp, _dp, _c.c_int, _dp]),
     ("ri_ccsd_iterate", _c.c_int, [_sysp, _dp, _dp, _c.POINTER(RICcsdOpts), _c.POINTER(RICcsdReport), _dp]),
+    ("ri_ccsd_triples", _c.c_int, [_sysp, _dp, _dp, _dblp, _dp]),
+    ("ri_ccsd_triples_flops", _c.c_double, [_c.c_int, _c.c_int]),
     ("ri_mlp_create", _c.c_void_p, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_mlp_destroy", None, [_c.c_void_p]),
     ("ri_mlp_num_params", _c.c_size_t, [_c.c_void_p]),

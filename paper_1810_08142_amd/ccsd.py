@@ -44,6 +44,21 @@ def energy(B, eps, o, t1, t2, stream=None) -> float:
     return e.value
 
 
+def triples(B, eps, o, t1, t2, stream=None) -> float:
+    """Perturbative triples energy E_(T) of CCSD(T) at the amplitudes (ri_ccsd_triples)."""
+    sy = _system(B, eps, o)
+    _need(t1, "t1", (o, sy.v))
+    _need(t2, "t2", (o, o, sy.v, sy.v))
+    e = ctypes.c_double()
+    _lib.check(_lib.lib().ri_ccsd_triples(ctypes.byref(sy), t1.data_ptr(), t2.data_ptr(), ctypes.byref(e),
+                                          _stream(stream)), "ri_ccsd_triples")
+    return e.value
+
+
+def triples_flops(o: int, v: int) -> float:
+    return float(_lib.lib().ri_ccsd_triples_flops(o, v))
+
+
 def residual(B, eps, o, t1, t2, ppl_precision="fp64", stream=None):
     """(Omega1 [o][v], Omega2 [o][o][v][v]) at the given amplitudes."""
     sy = _system(B, eps, o)

@@ -5,6 +5,7 @@
   python -m paper_1810_08142_amd.cli ttc --config c3 --scale naux [--polish 1e-6]
   python -m paper_1810_08142_amd.cli shard --config c4 --nshards 8 [--precision fp64|fp32|bf16x3]
   python -m paper_1810_08142_amd.cli ablation --config c2
+  python -m paper_1810_08142_amd.cli triples --config c5 [--scale naux] [--precision fp64|bf16x3]
 
 `ccsd` prints one JSON line with the report (energy, iterations, timings, scale
 used).  `ttc` (time to converged E_corr) solves one system four times -- FP64
@@ -16,7 +17,9 @@ the slowest and mean shard, with the R bytes one device would contribute to the
 all-gather that completes the call.  `ablation` times one ladder call in the paper's
 arrangement (ri_ppl_paper: full (a, b) build, i <= j pairs) against the tau+- form
 (ri_ppl, FP64) on the same inputs, with each one's own FLOP count and the largest
-difference between the two results.
+difference between the two results.  `triples` converges CCSD and evaluates the
+perturbative triples energy E_(T) (ri_ccsd_triples) at the result, with its time and
+FLOP rate.
 """
 from __future__ import annotations
 
@@ -53,6 +56,11 @@ def main(argv=None):
     t.add_argument("--tol", type=float, default=1e-8)
     t.add_argument("--tol-energy", type=float, default=1e-9)
     t.add_argument("--verbose", action="store_true")
+    tr = sub.add_parser("triples")
+    tr.add_argument("--config", default="c1")
+    tr.add_argument("--scale", default="naux")
+    tr.add_argument("--precision", default="fp64", help="ladder precision of the CCSD solve")
+    tr.add_argument("--tol", type=float, default=1e-8)
     ab = sub.add_parser("ablation")
     ab.add_argument("--config", default="c2")
     ab.add_argument("--repeat", type=int, default=2)
@@ -67,6 +75,8 @@ def main(argv=None):
         return _shard(args)
     if args.cmd == "ablation":
         return _ablation(args)
+    if args.cmd == "triples":
+        return _triples(args)
 
     import torch
 
@@ -152,6 +162,32 @@ def _inputs(config):
     tau = ppl.build_tau(t1, t2)
     B_vv = B[:, o:, o:].contiguous()
     return s.o, s.v, s.naux, B_vv, tau
+
+
+def _triples(args):
+    import torch
+
+    from . import ccsd
+    from .synthetic import CONFIGS, draw_system
+    cfg = CONFIGS[args.config]
+    s = draw_system(cfg["o"], cfg["v"], cfg["naux"], seed=cfg["seed"], scale=args.scale)
+    o, v = s.o, s.v
+    B = torch.from_numpy(s.B).to("cuda")
+    eps = torch.from_numpy(s.eps).to("cuda")
+    t1, t2, rep = ccsd.solve(B, eps, o, tol=args.tol, tol_energy=0.1 * args.tol, ppl_precision=args.precision,
+                             polish_residual=1e-6 if args.precision != "fp64" else 0.0)
+    print(json.dumps(dict(ccsd_iterations=rep.iterations, ccsd_seconds=rep.seconds_total, e_corr=rep.e_corr)),
+          file=sys.stderr, flush=True)
+    ccsd.triples(B, eps, o, t1, t2)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_t = ccsd.triples(B, eps, o, t1, t2)
+    dt = time.perf_counter() - t0
+    fl = ccsd.triples_flops(o, v)
+    print(json.dumps(dict(config=args.config, o=o, v=v, naux=s.naux, scale=s.scale, ccsd_precision=args.precision,
+                          ccsd_converged=rep.converged, e_corr=rep.e_corr, e_triples=e_t, triples_seconds=dt,
+                          triples_flop=fl, triples_tflops=fl / dt / 1e12)), flush=True)
+    return 0 if rep.converged else 3
 
 
 def _ablation(args):

@@ -69,3 +69,12 @@ def test_mlp_training_options_and_checks():
     r = (ctypes.c_double * 2)()
     assert L.ri_tau_pair_asymmetry(None, 2, 3, r, None) == 1
     assert L.ri_tau_pair_asymmetry(64, 0, 3, r, None) == 1
+
+
+def test_triples_argument_checks():
+    from paper_1810_08142_amd import _lib
+    L = _lib.lib()
+    e = ctypes.c_double()
+    assert L.ri_ccsd_triples(None, 8, 8, ctypes.byref(e), None) == 1
+    assert L.ri_ccsd_triples_flops(2, 3) == 2 * 3 * 4 * (2.0 * 81 + 2.0 * 27 * 2)
+    assert L.ri_ccsd_triples_flops(0, 3) == 0.0
