@@ -237,9 +237,9 @@ int ri_ccsd_iterate(const ri_system* sys, double* t1, double* t2, const ri_ccsd_
  *                               (V^{abc}_{ijk} - V^{cba}_{ijk}) / (3 D^{abc}_{ijk})
  * with W, V and D as defined there; written to *e_t (host).  The occupied triplets
  * i <= j <= k are visited once each (W and V of the other orderings are permutations
- * of theirs).  Cost ri_ccsd_triples_flops(o, v) = o(o+1)(o+2) (2 v^4 + 2 v^3 o) FLOP;
- * device workspace of o v^3 + o^3 v + o^2 v^2 + 2 v^3 doubles (plus small buffers) is
- * taken stream-ordered.  Synchronises stream; RI_E_NUMERIC if the energy is not
+ * of theirs).  Cost ri_ccsd_triples_flops(o, v) = o(o+1)(o+2) 2 v^3 (v+o) FLOP;
+ * device workspace of o v^2 (v+o) + o^2 v (v+o) + o^3 v + o^2 v^2 + 8 v^3 doubles
+ * (plus small buffers) is taken stream-ordered.  Synchronises stream; RI_E_NUMERIC if the energy is not
  * finite. */
 int ri_ccsd_triples(const ri_system* sys, const double* t1, const double* t2, double* e_t, void* stream);
 double ri_ccsd_triples_flops(int o, int v);

@@ -15,11 +15,12 @@
 // so the energy kernel evaluates it for each distinct ordering (i', j', k') from the
 // one W and V, reading them through permuted tiles.
 //
-// Per triplet: twelve GEMMs on the library's FP64 MFMA engine accumulate W [a][b][c]
-// (each of the six terms of P is one v^4 and one v^3 o product, written through a
-// permuted output view), a kernel forms V = W + the t1 terms, and a tiled kernel sums
-// the energy in a fixed order.  Integrals G[i][a][b][d] = (bd|ai), J[k][j][c][l] =
-// (ck|jl) and K[i][a][j][b] = (ia|jb) are built once from the RI factors.
+// Per triplet: six GEMMs on the library's FP64 MFMA engine, one per term of P, each
+// writing its term in its own natural layout (contiguous output rows; the o-sized sum
+// of a term rides along as extra columns of the summed index), a tiled kernel
+// symmetrises the six into W and forms V = W + the t1 terms, and a tiled kernel sums
+// the energy in a fixed order.  The GEMM operands (with (yd|xp) and (zr|ql) from the
+// RI factors) and (ia|jb) are built once.
 #include <cmath>
 #include <vector>
 
@@ -48,30 +49,15 @@ struct Orders {
   Order t[6];
 };
 
-// V[a][b][c] = W[a][b][c] + (jb|kc) t^a_i + (ia|kc) t^b_j + (ia|jb) t^c_k, c fastest
-__global__ __launch_bounds__(256) void make_v(const double* __restrict__ W, const double* __restrict__ K,
-                                              const double* __restrict__ t1, int o, int v, int i, int j, int k,
-                                              double* __restrict__ V) {
-  const long n = static_cast<long>(v) * v * v;
-  const long x = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
-  if (x >= n) return;
-  const int c = static_cast<int>(x % v);
-  const long ab = x / v;
-  const int b = static_cast<int>(ab % v), a = static_cast<int>(ab / v);
-  auto Kx = [&](int i1, int p1, int i2, int p2) { return K[((static_cast<long>(i1) * v + p1) * o + i2) * v + p2]; };
-  V[x] = W[x] + Kx(j, b, k, c) * t1[i * v + a] + Kx(i, a, k, c) * t1[j * v + b] + Kx(i, a, j, b) * t1[k * v + c];
-}
-
-// Energy of one triplet over the orderings in `ord`, summed per 8^3 tile of (a, b, c)
-// into part[tile].  Each block stages the six orientations of its tile triple of W
-// and V in LDS (tile[p] holds W[Z_p0 + u][Z_p1 + w][Z_p2 + z] for Z = (A0, B0, C0)),
-// so every permuted read is an LDS read.  grid nt^3 (nt = ceil(v/8)), block 512.
-__global__ __launch_bounds__(512) void energy_tiles(const double* __restrict__ W, const double* __restrict__ V,
-                                                    const double* __restrict__ eps, int o, int v, Orders ord,
-                                                    double* __restrict__ part) {
-  __shared__ double tw[6][TE][TE][TE];
-  __shared__ double tv[6][TE][TE][TE];
-  __shared__ double red[512];
+// W[a][b][c] = sum_p Y_p[y0][y1][y2] with y_m = (a, b, c)[perm(p, m)] (the six terms of
+// P, each computed in its own natural layout), and V = W + (jb|kc) t^a_i + (ia|kc) t^b_j
+// + (ia|jb) t^c_k.  Each block stages, term by term, the 8^3 tile of Y_p at the
+// permuted block coordinates in LDS and reads it transposed, so every global access
+// runs along c.  grid nt^3, block 512.
+__global__ __launch_bounds__(512) void assemble_wv(const double* __restrict__ Y, const double* __restrict__ K,
+                                                   const double* __restrict__ t1, int o, int v, int i, int j, int k,
+                                                   double* __restrict__ W, double* __restrict__ V) {
+  __shared__ double tile[TE][TE][TE];
   const int nt = (v + TE - 1) / TE;
   const long bid = blockIdx.x;
   const int Z0 = static_cast<int>(bid / (static_cast<long>(nt) * nt)) * TE;
@@ -79,6 +65,46 @@ __global__ __launch_bounds__(512) void energy_tiles(const double* __restrict__ W
   const int Z2 = static_cast<int>(bid % nt) * TE;
   const int t = threadIdx.x, u = t >> 6, w = (t >> 3) & 7, z = t & 7;
   auto Zof = [&](int m) { return m == 0 ? Z0 : (m == 1 ? Z1 : Z2); };
+  auto xl = [&](int m) { return m == 0 ? u : (m == 1 ? w : z); };
+  const long v3 = static_cast<long>(v) * v * v;
+  double acc = 0.0;
+  for (int p = 0; p < 6; ++p) {
+    const int y0 = Zof(perm_at(p, 0)) + u, y1 = Zof(perm_at(p, 1)) + w, y2 = Zof(perm_at(p, 2)) + z;
+    const bool in = y0 < v && y1 < v && y2 < v;
+    tile[u][w][z] = in ? Y[p * v3 + (static_cast<long>(y0) * v + y1) * v + y2] : 0.0;
+    __syncthreads();
+    acc += tile[xl(perm_at(p, 0))][xl(perm_at(p, 1))][xl(perm_at(p, 2))];
+    __syncthreads();
+  }
+  const int a = Z0 + u, b = Z1 + w, c = Z2 + z;
+  if (a < v && b < v && c < v) {
+    auto Kx = [&](int i1, int p1, int i2, int p2) { return K[((static_cast<long>(i1) * v + p1) * o + i2) * v + p2]; };
+    const long at = (static_cast<long>(a) * v + b) * v + c;
+    W[at] = acc;
+    V[at] = acc + Kx(j, b, k, c) * t1[i * v + a] + Kx(i, a, k, c) * t1[j * v + b] + Kx(i, a, j, b) * t1[k * v + c];
+  }
+}
+
+// index of the permutation (e0, e1, e2) in the order of perm_at
+__host__ __device__ inline int perm_index(int e0, int e1) { return 2 * e0 + (e1 > e0 ? e1 - 1 : e1); }
+
+// Energy of one triplet over the orderings in `ord`, summed per unordered triple of
+// 8-wide tiles {A, B, C} (A <= B <= C, packed in tiles[] as A | B << 10 | C << 20)
+// into part[block].  Each block stages the six orientations of its tile triple of W
+// and V in LDS (orientation p holds W[Z_p0 + u][Z_p1 + w][Z_p2 + z] for Z = (A, B, C)
+// in elements) and evaluates every distinct ordering s of the triple from them, so each
+// tile of W and V is read from memory once per triplet.  grid = number of tile
+// triples, block 512.
+__global__ __launch_bounds__(512) void energy_tiles(const double* __restrict__ W, const double* __restrict__ V,
+                                                    const double* __restrict__ eps, int o, int v, Orders ord,
+                                                    const int* __restrict__ tiles, double* __restrict__ part) {
+  __shared__ double tw[6][TE][TE][TE];
+  __shared__ double tv[6][TE][TE][TE];
+  __shared__ double red[512];
+  const int code = tiles[blockIdx.x];
+  const int bt[3] = {code & 1023, (code >> 10) & 1023, (code >> 20) & 1023};
+  const int t = threadIdx.x, u = t >> 6, w = (t >> 3) & 7, z = t & 7;
+  auto Zof = [&](int m) { return (m == 0 ? bt[0] : (m == 1 ? bt[1] : bt[2])) * TE; };
   for (int p = 0; p < 6; ++p) {
     const int y0 = Zof(perm_at(p, 0)) + u, y1 = Zof(perm_at(p, 1)) + w, y2 = Zof(perm_at(p, 2)) + z;
     const bool in = y0 < v && y1 < v && y2 < v;
@@ -87,20 +113,34 @@ __global__ __launch_bounds__(512) void energy_tiles(const double* __restrict__ W
     tv[p][u][w][z] = in ? V[at] : 0.0;
   }
   __syncthreads();
-  const int a = Z0 + u, b = Z1 + w, c = Z2 + z;
+  auto xl = [&](int m) { return m == 0 ? u : (m == 1 ? w : z); };  // local coordinate of a, b or c
   double acc = 0.0;
-  if (a < v && b < v && c < v) {
-    auto xl = [&](int m) { return m == 0 ? u : (m == 1 ? w : z); };  // local coordinate of a, b or c
-    auto rw = [&](int p) { return tw[p][xl(perm_at(p, 0))][xl(perm_at(p, 1))][xl(perm_at(p, 2))]; };
-    auto rv = [&](int p) { return tv[p][xl(perm_at(p, 0))][xl(perm_at(p, 1))][xl(perm_at(p, 2))]; };
-    const double evir = eps[o + a] + eps[o + b] + eps[o + c];
+  for (int sg = 0; sg < 6; ++sg) {
+    // skip an ordering of the tile triple that repeats an earlier one (equal tiles)
+    const int k0 = bt[perm_at(sg, 0)], k1 = bt[perm_at(sg, 1)], k2 = bt[perm_at(sg, 2)];
+    bool dup = false;
+    for (int s2 = 0; s2 < sg; ++s2)
+      dup = dup || (bt[perm_at(s2, 0)] == k0 && bt[perm_at(s2, 1)] == k1 && bt[perm_at(s2, 2)] == k2);
+    if (dup) continue;
+    const int a = k0 * TE + u, b = k1 * TE + w, c = k2 * TE + z;
+    if (a >= v || b >= v || c >= v) continue;
+    // element (a, b, c) of orientation sg; a read in orientation rho of (a, b, c) comes
+    // from tile sg o rho at local coordinates (x_rho0, x_rho1, x_rho2)
+    auto rd = [&](const double (*tt)[TE][TE][TE], int rho) {
+      const int r0 = perm_at(rho, 0), r1 = perm_at(rho, 1);
+      const int tau = perm_index(perm_at(sg, r0), perm_at(sg, r1));
+      return tt[tau][xl(r0)][xl(r1)][xl(perm_at(rho, 2))];
+    };
+    // D is symmetric in (i, j, k): one reciprocal serves every ordering
+    const double d = eps[ord.t[0].ip] + eps[ord.t[0].jp] + eps[ord.t[0].kp] - (eps[o + a] + eps[o + b] + eps[o + c]);
+    double sum = 0.0;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       if (q >= ord.n) break;
       const Order& r = ord.t[q];
-      const double d = eps[r.ip] + eps[r.jp] + eps[r.kp] - evir;
-      acc += (4.0 * rw(r.r1) + rw(r.r2) + rw(r.r3)) * (rv(r.r1) - rv(r.r4)) / (3.0 * d);
+      sum += (4.0 * rd(tw, r.r1) + rd(tw, r.r2) + rd(tw, r.r3)) * (rd(tv, r.r1) - rd(tv, r.r4));
     }
+    acc += sum / (3.0 * d);
   }
   red[t] = acc;
   __syncthreads();
@@ -108,7 +148,7 @@ __global__ __launch_bounds__(512) void energy_tiles(const double* __restrict__ W
     if (t < s) red[t] += red[t + s];
     __syncthreads();
   }
-  if (t == 0) part[bid] = red[0];
+  if (t == 0) part[blockIdx.x] = red[0];
 }
 
 // out[0] = sum of part[0..n) in a fixed order (one block)
@@ -123,13 +163,6 @@ __global__ __launch_bounds__(256) void sum_parts(const double* __restrict__ part
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];
-}
-
-// index of the permutation with elements (e0, e1, e2)
-inline int perm_index(int e0, int e1, int e2) {
-  for (int p = 0; p < 6; ++p)
-    if (perm_at(p, 0) == e0 && perm_at(p, 1) == e1 && perm_at(p, 2) == e2) return p;
-  return -1;
 }
 
 // The distinct orderings of (i, j, k) and their read tiles.
@@ -153,10 +186,10 @@ Orders orders_of(int i, int j, int k) {
     r.ip = key[0];
     r.jp = key[1];
     r.kp = key[2];
-    r.r1 = perm_index(inv[0], inv[1], inv[2]);
-    r.r2 = perm_index((inv[0] + 1) % 3, (inv[1] + 1) % 3, (inv[2] + 1) % 3);
-    r.r3 = perm_index((inv[0] + 2) % 3, (inv[1] + 2) % 3, (inv[2] + 2) % 3);
-    r.r4 = perm_index(2 - inv[0], 2 - inv[1], 2 - inv[2]);
+    r.r1 = perm_index(inv[0], inv[1]);
+    r.r2 = perm_index((inv[0] + 1) % 3, (inv[1] + 1) % 3);
+    r.r3 = perm_index((inv[0] + 2) % 3, (inv[1] + 2) % 3);
+    r.r4 = perm_index(2 - inv[0], 2 - inv[1]);
   }
   return out;
 }
@@ -171,7 +204,7 @@ extern "C" {
 double ri_ccsd_triples_flops(int o, int v) {
   if (o <= 0 || v <= 0) return 0.0;
   const double trip = o * (o + 1.0) * (o + 2.0) / 6.0, v3 = static_cast<double>(v) * v * v;
-  return trip * 6.0 * (2.0 * v3 * v + 2.0 * v3 * o);
+  return trip * 6.0 * 2.0 * v3 * (v + o);
 }
 
 int ri_ccsd_triples(const ri_system* sys, const double* t1, const double* t2, double* e_t, void* stream) {
@@ -183,23 +216,42 @@ int ri_ccsd_triples(const ri_system* sys, const double* t1, const double* t2, do
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int o = sys->o, v = sys->v, Q = sys->naux, n = o + v;
+  const int vo = (v + o + 15) / 16 * 16;  // summed index of a term, padded with zeros to 16
   const long nn = static_cast<long>(n) * n, vv = static_cast<long>(v) * v, v3 = vv * v;
   const int nt = (v + trip::TE - 1) / trip::TE;
-  const long ntiles = static_cast<long>(nt) * nt * nt;
+  if (nt > 1023) {
+    set_error("ri_ccsd_triples: v = %d is too large for the energy tiles", v);
+    return RI_E_ARG;
+  }
+  const long ntiles = static_cast<long>(nt) * nt * nt;        // assembly tiles (ordered)
+  const long ntri = static_cast<long>(nt) * (nt + 1) * (nt + 2) / 6;  // energy tile triples
   const long ntrip = static_cast<long>(o) * (o + 1) * (o + 2) / 6;
-  // G [o][v][v][v], J [o][o][v][o], K [o][v][o][v], W and V [v][v][v], tile partials, triplet sums
-  const size_t nG = static_cast<size_t>(o) * v3, nJ = static_cast<size_t>(o) * o * v * o,
-               nK = static_cast<size_t>(o) * v * o * v;
-  const size_t total = nG + nJ + nK + 2 * static_cast<size_t>(v3) + ntiles + ntrip;
+  // Each term of P, X(p, q, r; x, y, z) = sum_d (yd|xp) t2[r][q][z][d] - sum_l (zr|ql) t2[p][l][x][y],
+  // is one GEMM over the combined index e = (d, then l):
+  //   A[p][x][y][e] = (yd|xp) for e = d < v,  t2[p][l][x][y] for e = v + l,
+  //   Bt[r][q][z][e] = t2[r][q][z][d] for e = d < v,  -(zr|ql) for e = v + l.
+  // Buffers: A [o][v][v][v+o], Bt [o][o][v][v+o], J [o][o][v][o], K [o][v][o][v],
+  // Y [6][v][v][v] (the six terms), W and V [v][v][v], tile partials, triplet sums.
+  const size_t nA = static_cast<size_t>(o) * vv * vo, nBt = static_cast<size_t>(o) * o * v * vo,
+               nJ = static_cast<size_t>(o) * o * v * o, nK = static_cast<size_t>(o) * v * o * v;
+  const size_t total = nA + nBt + nJ + nK + 8 * static_cast<size_t>(v3) + ntri + ntrip + (ntri + 1) / 2;
   void* buf = nullptr;
   RI_TRY(dev_alloc(&buf, total * sizeof(double), s));
-  double* G = static_cast<double*>(buf);
-  double* J = G + nG;
+  double* A = static_cast<double*>(buf);
+  double* Bt = A + nA;
+  double* J = Bt + nBt;
   double* K = J + nJ;
-  double* W = K + nK;
+  double* Y = K + nK;
+  double* W = Y + 6 * v3;
   double* Vt = W + v3;
   double* part = Vt + v3;
-  double* et = part + ntiles;
+  double* et = part + ntri;
+  int* tl = reinterpret_cast<int*>(et + ntrip);
+  std::vector<int> tiles_host;
+  tiles_host.reserve(ntri);
+  for (int ta = 0; ta < nt; ++ta)
+    for (int tb = ta; tb < nt; ++tb)
+      for (int tc = tb; tc < nt; ++tc) tiles_host.push_back(ta | (tb << 10) | (tc << 20));
   int rc = RI_OK;
   {
     GemmArena arena;
@@ -210,48 +262,56 @@ int ri_ccsd_triples(const ri_system* sys, const double* t1, const double* t2, do
     const Tensor Bvo(B + static_cast<long>(o) * n, {Q, v, o}, {nn, n, 1});
     const Tensor Boo(B, {Q, o, o}, {nn, n, 1});
     const Tensor Bov(B + o, {Q, o, v}, {nn, n, 1});
+    const long sA2 = vo, sA1 = static_cast<long>(v) * vo, sA0 = vv * vo;  // strides of A
+    const long sB2 = vo, sB1 = static_cast<long>(v) * vo, sB0 = static_cast<long>(o) * v * vo;  // of Bt
     do {
-      // G[i][a][b][d] = (bd|ai), J[k][j][c][l] = (ck|jl), K[i][a][j][b] = (ia|jb)
-      if ((rc = einsum("Qbd,Qai->iabd", 1.0, Bvv, Bvo, 0.0, Tensor(G, {o, v, v, v}), arena, s))) break;
-      if ((rc = einsum("Qck,Qjl->kjcl", 1.0, Bvo, Boo, 0.0, Tensor(J, {o, o, v, o}), arena, s))) break;
+      if ((rc = check_hip(hipMemcpyAsync(tl, tiles_host.data(), ntri * sizeof(int), hipMemcpyHostToDevice, s),
+                          "triples tiles")))
+        break;
+      // zero padding of the summed index (columns v + o .. vo - 1)
+      if ((rc = check_hip(hipMemsetAsync(A, 0, (nA + nBt) * sizeof(double), s), "triples clear"))) break;
+      // A[p][x][y][d] = (yd|xp)
+      if ((rc = einsum("Qyd,Qxp->pxyd", 1.0, Bvv, Bvo, 0.0, Tensor(A, {o, v, v, v}, {sA0, sA1, sA2, 1}), arena,
+                       s)))
+        break;
+      // A[p][x][y][v + l] = t2[p][l][x][y]
+      if ((rc = axpby_perm("plxy->pxyl", 1.0, Tensor(t2, {o, o, v, v}), 0.0,
+                           Tensor(A + v, {o, v, v, o}, {sA0, sA1, sA2, 1}), s)))
+        break;
+      // J[r][q][z][l] = (zr|ql); Bt[r][q][z][d] = t2[r][q][z][d], Bt[r][q][z][v + l] = -J[r][q][z][l]
+      if ((rc = einsum("Qzr,Qql->rqzl", 1.0, Bvo, Boo, 0.0, Tensor(J, {o, o, v, o}), arena, s))) break;
+      if ((rc = axpby_perm("rqzd->rqzd", 1.0, Tensor(t2, {o, o, v, v}), 0.0,
+                           Tensor(Bt, {o, o, v, v}, {sB0, sB1, sB2, 1}), s)))
+        break;
+      if ((rc = axpby_perm("rqzl->rqzl", -1.0, Tensor(J, {o, o, v, o}), 0.0,
+                           Tensor(Bt + v, {o, o, v, o}, {sB0, sB1, sB2, 1}), s)))
+        break;
+      // K[i][a][j][b] = (ia|jb)
       if ((rc = einsum("Qia,Qjb->iajb", 1.0, Bov, Bov, 0.0, Tensor(K, {o, v, o, v}), arena, s))) break;
-      const Tensor Wt(W, {v, v, v});
-      auto Gp = [&](int p) { return Tensor(G + p * v3, {v, v, v}); };
-      auto T2 = [&](int r, int q) { return Tensor(t2 + (static_cast<long>(r) * o + q) * vv, {v, v}); };
-      auto Jrq = [&](int r, int q) { return Tensor(J + (static_cast<long>(r) * o + q) * v * o, {v, o}); };
-      auto T2p = [&](int p) { return Tensor(t2 + static_cast<long>(p) * o * vv, {o, v, v}); };
       long tix = 0;
       for (int i = 0; i < o && rc == RI_OK; ++i)
         for (int j = i; j < o && rc == RI_OK; ++j)
           for (int k = j; k < o && rc == RI_OK; ++k, ++tix) {
-            // the six terms (p, q, r; x, y, z) of P, each
-            //   W[a][b][c] += sum_d G[p][x][y][d] t2[r][q][z][d] - sum_l J[r][q][z][l] t2[p][l][x][y]
-            struct Term {
-              int p, q, r;
-              const char* first;
-              const char* second;
-            };
-            const Term terms[6] = {
-                {i, j, k, "abd,cd->abc", "lab,cl->abc"}, {i, k, j, "acd,bd->abc", "lac,bl->abc"},
-                {k, i, j, "cad,bd->abc", "lca,bl->abc"}, {k, j, i, "cbd,ad->abc", "lcb,al->abc"},
-                {j, k, i, "bcd,ad->abc", "lbc,al->abc"}, {j, i, k, "bad,cd->abc", "lba,cl->abc"},
-            };
+            // term of permutation m: (p, q, r) = the triplet and (x, y, z) = (a, b, c), both
+            // permuted by m; its natural layout Y_m[x][y][z]
+            const int x3[3] = {i, j, k};
             for (int m = 0; m < 6 && rc == RI_OK; ++m) {
-              const Term& tm = terms[m];
-              rc = einsum(tm.first, 1.0, Gp(tm.p), T2(tm.r, tm.q), m == 0 ? 0.0 : 1.0, Wt, arena, s);
-              if (rc == RI_OK) rc = einsum(tm.second, -1.0, T2p(tm.p), Jrq(tm.r, tm.q), 1.0, Wt, arena, s);
+              const int pp = x3[trip::perm_at(m, 0)], qq = x3[trip::perm_at(m, 1)], rr = x3[trip::perm_at(m, 2)];
+              rc = einsum("xye,ze->xyz", 1.0, Tensor(A + pp * sA0, {v, v, vo}, {sA1, sA2, 1}),
+                          Tensor(Bt + (static_cast<long>(rr) * o + qq) * sB1, {v, vo}, {sB2, 1}), 0.0,
+                          Tensor(Y + m * v3, {v, v, v}), arena, s);
             }
             if (rc) break;
             {
-              ProfScope ps(s, "triples_make_v", 0.0, 24.0 * v3);
-              trip::make_v<<<static_cast<unsigned>((v3 + 255) / 256), 256, 0, s>>>(W, K, t1, o, v, i, j, k, Vt);
-              if ((rc = check_launch("triples_make_v"))) break;
+              ProfScope ps(s, "triples_assemble", 0.0, 8.0 * 8.0 * v3);
+              trip::assemble_wv<<<static_cast<unsigned>(ntiles), 512, 0, s>>>(Y, K, t1, o, v, i, j, k, W, Vt);
+              if ((rc = check_launch("triples_assemble"))) break;
             }
             {
-              ProfScope ps(s, "triples_energy", 0.0, 96.0 * v3);
+              ProfScope ps(s, "triples_energy", 0.0, 16.0 * v3);
               const trip::Orders ord = trip::orders_of(i, j, k);
-              trip::energy_tiles<<<static_cast<unsigned>(ntiles), 512, 0, s>>>(W, Vt, sys->eps, o, v, ord, part);
-              trip::sum_parts<<<1, 256, 0, s>>>(part, ntiles, et + tix);
+              trip::energy_tiles<<<static_cast<unsigned>(ntri), 512, 0, s>>>(W, Vt, sys->eps, o, v, ord, tl, part);
+              trip::sum_parts<<<1, 256, 0, s>>>(part, ntri, et + tix);
               if ((rc = check_launch("triples_energy"))) break;
             }
           }
