@@ -61,6 +61,8 @@ def main(argv=None):
     tr.add_argument("--scale", default="naux")
     tr.add_argument("--precision", default="fp64", help="ladder precision of the CCSD solve")
     tr.add_argument("--tol", type=float, default=1e-8)
+    tr.add_argument("--kernels", action="store_true",
+                    help="one more call under the library's event profiler; per-kernel times on stderr")
     ab = sub.add_parser("ablation")
     ab.add_argument("--config", default="c2")
     ab.add_argument("--repeat", type=int, default=2)
@@ -184,6 +186,14 @@ def _triples(args):
     e_t = ccsd.triples(B, eps, o, t1, t2)
     dt = time.perf_counter() - t0
     fl = ccsd.triples_flops(o, v)
+    if args.kernels:
+        from . import _lib
+        _lib.prof_enable(True)
+        _lib.prof_report()
+        ccsd.triples(B, eps, o, t1, t2)
+        _lib.prof_enable(False)
+        for r in sorted(_lib.prof_report(), key=lambda r: -r["ms"]):
+            print(json.dumps(r), file=sys.stderr, flush=True)
     print(json.dumps(dict(config=args.config, o=o, v=v, naux=s.naux, scale=s.scale, ccsd_precision=args.precision,
                           ccsd_converged=rep.converged, e_corr=rep.e_corr, e_triples=e_t, triples_seconds=dt,
                           triples_flop=fl, triples_tflops=fl / dt / 1e12)), flush=True)
