@@ -73,6 +73,7 @@ _SIGS = [
     ("ri_ccsd_residual", _c.c_int, [_sysp, _dp, _dp, _dp, _dp, _c.c_int, _dp]),
     ("ri_ccsd_iterate", _c.c_int, [_sysp, _dp, _dp, _c.POINTER(RICcsdOpts), _c.POINTER(RICcsdReport), _dp]),
     ("ri_ccsd_triples", _c.c_int, [_sysp, _dp, _dp, _dblp, _dp]),
+    ("ri_ccsd_triples_ex", _c.c_int, [_sysp, _dp, _dp, _c.c_int, _dblp, _dp]),
     ("ri_ccsd_triples_flops", _c.c_double, [_c.c_int, _c.c_int]),
     ("ri_mlp_create", _c.c_void_p, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_mlp_destroy", None, [_c.c_void_p]),

@@ -44,14 +44,15 @@ def energy(B, eps, o, t1, t2, stream=None) -> float:
     return e.value
 
 
-def triples(B, eps, o, t1, t2, stream=None) -> float:
-    """Perturbative triples energy E_(T) of CCSD(T) at the amplitudes (ri_ccsd_triples)."""
+def triples(B, eps, o, t1, t2, precision="fp64", stream=None) -> float:
+    """Perturbative triples energy E_(T) of CCSD(T) at the amplitudes (ri_ccsd_triples_ex);
+    precision "fp64" or "fp32" (the term GEMMs)."""
     sy = _system(B, eps, o)
     _need(t1, "t1", (o, sy.v))
     _need(t2, "t2", (o, o, sy.v, sy.v))
     e = ctypes.c_double()
-    _lib.check(_lib.lib().ri_ccsd_triples(ctypes.byref(sy), t1.data_ptr(), t2.data_ptr(), ctypes.byref(e),
-                                          _stream(stream)), "ri_ccsd_triples")
+    _lib.check(_lib.lib().ri_ccsd_triples_ex(ctypes.byref(sy), t1.data_ptr(), t2.data_ptr(), _prec(precision),
+                                             ctypes.byref(e), _stream(stream)), "ri_ccsd_triples")
     return e.value
 
 

@@ -61,6 +61,7 @@ def main(argv=None):
     tr.add_argument("--scale", default="naux")
     tr.add_argument("--precision", default="fp64", help="ladder precision of the CCSD solve")
     tr.add_argument("--tol", type=float, default=1e-8)
+    tr.add_argument("--triples-precision", default="fp64", help="arithmetic of the (T) term GEMMs: fp64 or fp32")
     tr.add_argument("--kernels", action="store_true",
                     help="one more call under the library's event profiler; per-kernel times on stderr")
     ab = sub.add_parser("ablation")
@@ -180,22 +181,24 @@ def _triples(args):
                              polish_residual=1e-6 if args.precision != "fp64" else 0.0)
     print(json.dumps(dict(ccsd_iterations=rep.iterations, ccsd_seconds=rep.seconds_total, e_corr=rep.e_corr)),
           file=sys.stderr, flush=True)
-    ccsd.triples(B, eps, o, t1, t2)  # warm-up
+    tp = args.triples_precision
+    ccsd.triples(B, eps, o, t1, t2, precision=tp)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e_t = ccsd.triples(B, eps, o, t1, t2)
+    e_t = ccsd.triples(B, eps, o, t1, t2, precision=tp)
     dt = time.perf_counter() - t0
     fl = ccsd.triples_flops(o, v)
     if args.kernels:
         from . import _lib
         _lib.prof_enable(True)
         _lib.prof_report()
-        ccsd.triples(B, eps, o, t1, t2)
+        ccsd.triples(B, eps, o, t1, t2, precision=tp)
         _lib.prof_enable(False)
         for r in sorted(_lib.prof_report(), key=lambda r: -r["ms"]):
             print(json.dumps(r), file=sys.stderr, flush=True)
     print(json.dumps(dict(config=args.config, o=o, v=v, naux=s.naux, scale=s.scale, ccsd_precision=args.precision,
-                          ccsd_converged=rep.converged, e_corr=rep.e_corr, e_triples=e_t, triples_seconds=dt,
+                          ccsd_converged=rep.converged, e_corr=rep.e_corr, triples_precision=tp, e_triples=e_t,
+                          triples_seconds=dt,
                           triples_flop=fl, triples_tflops=fl / dt / 1e12)), flush=True)
     return 0 if rep.converged else 3
 

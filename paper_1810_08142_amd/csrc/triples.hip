@@ -207,11 +207,16 @@ double ri_ccsd_triples_flops(int o, int v) {
   return trip * 6.0 * 2.0 * v3 * (v + o);
 }
 
-int ri_ccsd_triples(const ri_system* sys, const double* t1, const double* t2, double* e_t, void* stream) {
+int ri_ccsd_triples_ex(const ri_system* sys, const double* t1, const double* t2, int precision, double* e_t,
+                       void* stream) {
   clear_error();
   RI_TRY(cc::check_system(sys, "ri_ccsd_triples"));
   if (!t1 || !t2 || !e_t) {
     set_error("ri_ccsd_triples: null pointer argument");
+    return RI_E_ARG;
+  }
+  if (precision != RI_PREC_FP64 && precision != RI_PREC_FP32) {
+    set_error("ri_ccsd_triples: precision %d is not FP64 or FP32", precision);
     return RI_E_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -299,7 +304,7 @@ int ri_ccsd_triples(const ri_system* sys, const double* t1, const double* t2, do
               const int pp = x3[trip::perm_at(m, 0)], qq = x3[trip::perm_at(m, 1)], rr = x3[trip::perm_at(m, 2)];
               rc = einsum("xye,ze->xyz", 1.0, Tensor(A + pp * sA0, {v, v, vo}, {sA1, sA2, 1}),
                           Tensor(Bt + (static_cast<long>(rr) * o + qq) * sB1, {v, vo}, {sB2, 1}), 0.0,
-                          Tensor(Y + m * v3, {v, v, v}), arena, s);
+                          Tensor(Y + m * v3, {v, v, v}), arena, s, precision);
             }
             if (rc) break;
             {
@@ -333,6 +338,10 @@ int ri_ccsd_triples(const ri_system* sys, const double* t1, const double* t2, do
   }
   dev_free(buf, s);
   return rc;
+}
+
+int ri_ccsd_triples(const ri_system* sys, const double* t1, const double* t2, double* e_t, void* stream) {
+  return ri_ccsd_triples_ex(sys, t1, t2, RI_PREC_FP64, e_t, stream);
 }
 
 }  // extern "C"

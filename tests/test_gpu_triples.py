@@ -47,3 +47,22 @@ def test_triples_at_converged_ccsd_and_t1_part():
     got2 = ccsd.triples(B, eps, o, torch.zeros_like(t1), t2)
     assert abs(got2 - ref2) <= 1e-10 * abs(ref2)
     assert ccsd.triples_flops(o, v) == o * (o + 1) * (o + 2) * (2.0 * v**4 + 2.0 * v**3 * o)
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(3, 24, 30, 7), (4, 33, 40, 8)])
+def test_triples_fp32_gemms_within_their_rounding(o, v, naux, seed, monkeypatch):
+    """With the term GEMMs in FP32 (forced onto the 128 x 128 tile kernel at these
+    small sizes), E_(T) stays within 1e-6 of its size of the oracle, and does differ
+    from the FP64 result (the FP32 path really runs)."""
+    from paper_1810_08142_amd import ccsd
+    monkeypatch.setenv("RI_GEMM_LARGE_MIN_TILES", "1")
+    s = draw_system(o, v, naux, seed=seed, scale=0.3)
+    t1 = draw_matrix((o, v), seed + 1, 0.05)
+    t2 = draw_pair_symmetric(o, v, seed + 2, 0.05)
+    ref = oc.triples(s.B, s.eps, o, t1, t2)
+    args = (dev(s.B), dev(s.eps), o, dev(t1), dev(t2))
+    e64 = ccsd.triples(*args)
+    e32 = ccsd.triples(*args, precision="fp32")
+    assert abs(e64 - ref) <= 1e-10 * abs(ref)
+    assert abs(e32 - ref) <= 1e-6 * abs(ref)
+    assert e32 != e64
