@@ -114,6 +114,28 @@ int ri_ppl_shard(const double* B_vv, const double* tau, int o, int v, int naux, 
 int ri_ppl_paper(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream);
 double ri_ppl_paper_flops(int o, int v, int naux);
 
+/* The ladder of ri_ppl, FP64, for factors symmetric in their two virtual indices
+ * (B_vv[Q][a][c] == B_vv[Q][c][a], the bare integrals of eq. RIM; not the t1-dressed
+ * factors of the CCSD residual).  Then (ac|bd) has the eight-fold symmetry of real
+ * two-electron integrals (Sec. II.C) and the integral matrix of the tau+- form is
+ * symmetric under the exchange of the (ab) and (cd) pairs: each slab of (ab) block
+ * pairs builds only the (cd) block pairs from its own first one on and uses every
+ * built element twice, once for its own (ab) rows and once, through a second FP64
+ * product, for the later (cd) rows.  With the default of at least 8 slab steps
+ * (environment RI_PPL_SYM_SLABS) the build costs about 9/16 of ri_ppl's; the
+ * contraction FLOP are unchanged.  Arguments, layouts, accumulation into R, the use of
+ * tau's pair-symmetric part and the error codes are those of ri_ppl; the result agrees
+ * with ri_ppl to rounding (the summation order differs).  The call first measures the
+ * factors' asymmetry on `stream` (synchronising it) and returns RI_E_ARG, leaving R
+ * untouched, unless max |B_ac - B_ca| <= 1e-12 max |B|.  Device workspace of about
+ * ri_ppl_workspace_bytes(o, v, naux, RI_PREC_FP64) plus about v^2 o^2 / 2 doubles of
+ * second-product accumulators is taken stream-ordered for the call. */
+int ri_ppl_sym(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream);
+/* Algorithmic FLOP of one ri_ppl_sym call (build and both products over its slab
+ * schedule, which depends on RI_PPL_W_BYTES, RI_PPL_SLAB_PAIRS and RI_PPL_SYM_SLABS);
+ * 0 on invalid arguments. */
+double ri_ppl_sym_flops(int o, int v, int naux);
+
 /* Workspace bytes ri_ppl_ex needs for these sizes (0 on invalid arguments). */
 size_t ri_ppl_workspace_bytes(int o, int v, int naux, int precision);
 

@@ -4,7 +4,7 @@
                                         [--polish 1e-6] [--check-fp64] [--model net.bin]
   python -m paper_1810_08142_amd.cli ttc --config c3 --scale naux [--polish 1e-6]
   python -m paper_1810_08142_amd.cli shard --config c4 --nshards 8 [--precision fp64|fp32|bf16x3]
-  python -m paper_1810_08142_amd.cli ablation --config c2
+  python -m paper_1810_08142_amd.cli ablation --config c2 [--forms tau_pm,paper,sym]
   python -m paper_1810_08142_amd.cli triples --config c5 [--scale naux] [--precision fp64|bf16x3]
 
 `ccsd` prints one JSON line with the report (energy, iterations, timings, scale
@@ -16,8 +16,9 @@ per-device work of an n-device split over the (ab) slabs) one after another and 
 the slowest and mean shard, with the R bytes one device would contribute to the
 all-gather that completes the call.  `ablation` times one ladder call in the paper's
 arrangement (ri_ppl_paper: full (a, b) build, i <= j pairs) against the tau+- form
-(ri_ppl, FP64) on the same inputs, with each one's own FLOP count and the largest
-difference between the two results.  `triples` converges CCSD and evaluates the
+(ri_ppl, FP64) on the same inputs, and the exchange-symmetric form (ri_ppl_sym: about
+half the build) beside them, with each one's own FLOP count and the largest
+difference of each result from ri_ppl's.  `triples` converges CCSD and evaluates the
 perturbative triples energy E_(T) (ri_ccsd_triples) at the result, with its time and
 FLOP rate.
 """
@@ -67,6 +68,7 @@ def main(argv=None):
     ab = sub.add_parser("ablation")
     ab.add_argument("--config", default="c2")
     ab.add_argument("--repeat", type=int, default=2)
+    ab.add_argument("--forms", default="tau_pm,paper,sym", help="comma list of tau_pm, paper, sym")
     sh = sub.add_parser("shard")
     sh.add_argument("--config", default="c4")
     sh.add_argument("--nshards", type=int, default=8)
@@ -210,8 +212,12 @@ def _ablation(args):
     o, v, naux, B_vv, tau = _inputs(args.config)
     out = dict(config=args.config, o=o, v=v, naux=naux)
     res = {}
-    for name, call, fl in (("tau_pm", lambda R: ppl.ppl(B_vv, tau, R), ppl.flops(o, v, naux)),
-                           ("paper", lambda R: ppl.ppl_paper(B_vv, tau, R), ppl.paper_flops(o, v, naux))):
+    forms = {"tau_pm": (lambda R: ppl.ppl(B_vv, tau, R), ppl.flops(o, v, naux)),
+             "paper": (lambda R: ppl.ppl_paper(B_vv, tau, R), ppl.paper_flops(o, v, naux)),
+             "sym": (lambda R: ppl.ppl_sym(B_vv, tau, R), ppl.sym_flops(o, v, naux))}
+    names = ["tau_pm"] + [f for f in args.forms.split(",") if f != "tau_pm"]
+    for name in names:
+        call, fl = forms[name]
         R = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
         call(R)  # warm-up (and the result compared below)
         torch.cuda.synchronize()
@@ -229,9 +235,10 @@ def _ablation(args):
         res[name] = R
         out[name] = dict(ms=best, flop=fl, tflops=fl / (best * 1e-3) / 1e12)
         print(json.dumps({name: out[name]}), file=sys.stderr, flush=True)
-    d = (res["paper"] - res["tau_pm"]).abs().max().item()
-    out["max_abs_diff_rel"] = d / res["tau_pm"].abs().max().item()
-    out["paper_over_tau_pm_time"] = out["paper"]["ms"] / out["tau_pm"]["ms"]
+    rmax = res["tau_pm"].abs().max().item()
+    for name in names[1:]:
+        out[f"{name}_max_abs_diff_rel"] = (res[name] - res["tau_pm"]).abs().max().item() / rmax
+        out[f"{name}_over_tau_pm_time"] = out[name]["ms"] / out["tau_pm"]["ms"]
     print(json.dumps(out), flush=True)
     return 0
 

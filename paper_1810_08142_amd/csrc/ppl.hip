@@ -33,6 +33,7 @@
 #include <cmath>
 #include <cstdlib>
 
+#include "gemm.h"
 #include "ppl_shared.h"
 
 namespace ri {
@@ -148,7 +149,8 @@ __global__ __launch_bounds__(256) void pack_tau_f32(const double* __restrict__ t
 // (Cb, Db).  Eight waves; wave w owns c in {2*(w>>1), +1} and d in {4*(w&1) .. +3}
 // of the quarter and accumulates (ac|bd) and (ad|bc) as 16x16 (a, b) MFMA tiles.
 // LDS holds, per KC-wide Q chunk, Bc for the 16 c/d rows x (16 a + 16 b) columns.
-// grid (nbp*4, slab_pairs), block 512
+// The launch covers cd block pairs pcd0 .. nbp-1 (rows of the others are not written).
+// grid ((nbp - pcd0)*4, slab_pairs), block 512
 // D: the workgroups of diagonal ab block pairs (Ab == Bb), blockIdx.y counting them
 // from block Ab = diag_y0; otherwise blockIdx.y is the slab's pair and diagonal pairs
 // exit at once.  In a diagonal pair a and b run over the same block, so the (ad|bc)
@@ -156,7 +158,8 @@ __global__ __launch_bounds__(256) void pack_tau_f32(const double* __restrict__ t
 // epilogue reads it back transposed through LDS.
 template <class T, bool D>
 __device__ __forceinline__ void build_body(const T* __restrict__ Bc, int naux_p, int vp, long slab0, long slab_M,
-                                           int want_minus, int diag_y0, T* __restrict__ Wp, T* __restrict__ Wm) {
+                                           int want_minus, int diag_y0, long pcd0, T* __restrict__ Wp,
+                                           T* __restrict__ Wm) {
   typedef Mfma<T> MF;
   typedef typename MF::vec_t vec_t;
   constexpr int VEC = 16 / sizeof(T);          // elements per 16-byte load
@@ -165,7 +168,7 @@ __device__ __forceinline__ void build_body(const T* __restrict__ Bc, int naux_p,
   __shared__ T lds[2][16][KC][32];  // [buf][x: 8 c then 8 d][k][e: 16 a then 16 b]
   static_assert(2 * 16 * KC * 32 >= 8 * 8 * 256, "the staging buffer holds the transposed tiles");
   const int quarter = blockIdx.x & 3;
-  const long pcd = blockIdx.x >> 2;
+  const long pcd = pcd0 + (blockIdx.x >> 2);
   int Cb, Db, Ab, Bb;
   tri_decode(pcd, Cb, Db);
   long pab_loc;
@@ -317,24 +320,20 @@ __device__ __forceinline__ void build_body(const T* __restrict__ Bc, int naux_p,
   }
 }
 __global__ __launch_bounds__(512) void build_w_f64(const double* __restrict__ Bc, int naux_p, int vp, long slab0,
-                                                   long slab_M, int want_minus, int diag_y0, double* __restrict__ Wp,
-                                                   double* __restrict__ Wm) {
-  build_body<double, false>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, Wp, Wm);
+    long slab_M, int want_minus, int diag_y0, long pcd0, double* __restrict__ Wp, double* __restrict__ Wm) {
+  build_body<double, false>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, pcd0, Wp, Wm);
 }
 __global__ __launch_bounds__(512) void build_w_f64_diag(const double* __restrict__ Bc, int naux_p, int vp, long slab0,
-                                                        long slab_M, int want_minus, int diag_y0,
-                                                        double* __restrict__ Wp, double* __restrict__ Wm) {
-  build_body<double, true>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, Wp, Wm);
+    long slab_M, int want_minus, int diag_y0, long pcd0, double* __restrict__ Wp, double* __restrict__ Wm) {
+  build_body<double, true>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, pcd0, Wp, Wm);
 }
 __global__ __launch_bounds__(512) void build_w_f32(const float* __restrict__ Bc, int naux_p, int vp, long slab0,
-                                                   long slab_M, int want_minus, int diag_y0, float* __restrict__ Wp,
-                                                   float* __restrict__ Wm) {
-  build_body<float, false>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, Wp, Wm);
+    long slab_M, int want_minus, int diag_y0, long pcd0, float* __restrict__ Wp, float* __restrict__ Wm) {
+  build_body<float, false>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, pcd0, Wp, Wm);
 }
 __global__ __launch_bounds__(512) void build_w_f32_diag(const float* __restrict__ Bc, int naux_p, int vp, long slab0,
-                                                        long slab_M, int want_minus, int diag_y0,
-                                                        float* __restrict__ Wp, float* __restrict__ Wm) {
-  build_body<float, true>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, Wp, Wm);
+    long slab_M, int want_minus, int diag_y0, long pcd0, float* __restrict__ Wp, float* __restrict__ Wm) {
+  build_body<float, true>(Bc, naux_p, vp, slab0, slab_M, want_minus, diag_y0, pcd0, Wp, Wm);
 }
 
 // ---------------------------------------------------------------- 3b. contract
@@ -552,6 +551,7 @@ struct Plan {
   size_t esize;  // bytes per element of the staged operands (8 FP64, 4 FP32)
   long zrows_p, zrows_m;  // largest splits x rows of one contraction launch (sizes S and A)
   size_t n_Bc, n_Tp, n_Tm, n_W, n_S, n_A;
+  size_t n_S2, n_A2;  // exchange-symmetric form only: second-product accumulators over all slots
   size_t bytes;
 };
 
@@ -577,7 +577,9 @@ static long max_split_rows(const Plan& p, int ncol, int ntw) {
   return best;
 }
 
-static bool make_plan(int o, int v, int naux, size_t esize, Plan& p) {
+// sym: the plan of the exchange-symmetric form (smaller slabs, second-product
+// accumulators); see run_sym.
+static bool make_plan(int o, int v, int naux, size_t esize, Plan& p, bool sym = false) {
   if (o <= 0 || v <= 0 || naux <= 0) return false;
   if (o > 4096 || v > 65536 || naux > (1 << 24)) return false;
   p.o = o;
@@ -602,6 +604,10 @@ static bool make_plan(int o, int v, int naux, size_t esize, Plan& p) {
   bp = bp > 65535 ? 65535 : bp;
   const long cap = env_long("RI_PPL_SLAB_PAIRS", bp);
   p.slab_bp = cap < bp ? cap : bp;
+  if (sym) {  // at least RI_PPL_SYM_SLABS (8) slabs: the build is (1 + 1/slabs)/2 of the full one
+    const long ns = env_long("RI_PPL_SYM_SLABS", 8);
+    p.slab_bp = std::min(p.slab_bp, (p.nbp + ns - 1) / ns);
+  }
   p.slab_M = p.slab_bp * 256;
   p.n_Bc = static_cast<size_t>(p.vp) * p.naux_p * p.vp;
   p.n_Tp = static_cast<size_t>(p.K) * p.NP;
@@ -611,8 +617,10 @@ static bool make_plan(int o, int v, int naux, size_t esize, Plan& p) {
   p.zrows_m = max_split_rows(p, p.NM, p.ntw_m);
   p.n_S = static_cast<size_t>(p.zrows_p) * p.NP;
   p.n_A = static_cast<size_t>(p.zrows_m) * p.NM;
+  p.n_S2 = sym ? static_cast<size_t>(p.K) * p.NP : 0;
+  p.n_A2 = sym ? static_cast<size_t>(p.K) * p.NM : 0;
   size_t b = 0;
-  for (size_t n : {p.n_Bc, p.n_Tp, p.n_Tm, p.n_W, p.pm > 0 ? p.n_W : 0, p.n_S, p.n_A})
+  for (size_t n : {p.n_Bc, p.n_Tp, p.n_Tm, p.n_W, p.pm > 0 ? p.n_W : 0, p.n_S, p.n_A, p.n_S2, p.n_A2})
     b = round_up(b, 256) + n * esize;
   p.bytes = round_up(b, 256);
   return true;
@@ -634,12 +642,13 @@ struct K64 {
   static void pack_k(dim3 g, hipStream_t s, const double* tau, int o, int v, int ncol, int sign, T* out) {
     pack_tau_f64<<<g, 256, 0, s>>>(tau, o, v, ncol, sign, out);
   }
-  static void build_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, T* Wp, T* Wm) {
-    build_w_f64<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, 0, Wp, Wm);
+  static void build_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, long pcd0,
+                      T* Wp, T* Wm) {
+    build_w_f64<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, 0, pcd0, Wp, Wm);
   }
   static void build_diag_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, int y0,
-                           T* Wp, T* Wm) {
-    build_w_f64_diag<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, y0, Wp, Wm);
+                           long pcd0, T* Wp, T* Wm) {
+    build_w_f64_diag<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, y0, pcd0, Wp, Wm);
   }
   template <int NTW>
   static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C, long kz,
@@ -662,12 +671,13 @@ struct K32 {
   static void pack_k(dim3 g, hipStream_t s, const double* tau, int o, int v, int ncol, int sign, T* out) {
     pack_tau_f32<<<g, 256, 0, s>>>(tau, o, v, ncol, sign, out);
   }
-  static void build_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, T* Wp, T* Wm) {
-    build_w_f32<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, 0, Wp, Wm);
+  static void build_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, long pcd0,
+                      T* Wp, T* Wm) {
+    build_w_f32<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, 0, pcd0, Wp, Wm);
   }
   static void build_diag_k(dim3 g, hipStream_t s, const T* Bc, int np, int vp, long slab0, long sM, int wm, int y0,
-                           T* Wp, T* Wm) {
-    build_w_f32_diag<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, y0, Wp, Wm);
+                           long pcd0, T* Wp, T* Wm) {
+    build_w_f32_diag<<<g, 512, 0, s>>>(Bc, np, vp, slab0, sM, wm, y0, pcd0, Wp, Wm);
   }
   template <int NTW>
   static void contract_k(dim3 g, hipStream_t s, const T* W, const T* Tt, long K, long M, int ncol, T* C, long kz,
@@ -697,20 +707,11 @@ static void launch_contract(int ntw, const typename KS::T* W, const typename KS:
   }
 }
 
+// Steps 1 and 2: factors into their operand layout, tau into T+ and T-.
 template <class KS>
-static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const double* tau, double* R, void* ws,
-                    int shard, int nshards, hipStream_t s) {
-  typedef typename KS::T T;
-  Carve cv(ws, p.bytes);
-  T* Bc = cv.take<T>(p.n_Bc);
-  T* Tp = cv.take<T>(p.n_Tp);
-  T* Tm = cv.take<T>(p.n_Tm);
-  T* Wp = cv.take<T>(p.n_W);
-  T* Wm = cv.take<T>(p.pm > 0 ? p.n_W : 0);
-  T* S = cv.take<T>(p.n_S);
-  T* A = cv.take<T>(p.n_A);
-
-  const double es = static_cast<double>(sizeof(T));
+static int stage_inputs(const Plan& p, const double* B_vv, long qs, long rs, const double* tau,
+                        typename KS::T* Bc, typename KS::T* Tp, typename KS::T* Tm, hipStream_t s) {
+  const double es = static_cast<double>(sizeof(typename KS::T));
   const double vv = static_cast<double>(p.v) * p.v, oo = static_cast<double>(p.o) * p.o;
   const double pv = p.v * (p.v + 1.0) / 2, pvm = p.v * (p.v - 1.0) / 2;
   {
@@ -727,6 +728,25 @@ static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const d
       RI_TRY(check_launch(KS::pack));
     }
   }
+  return RI_OK;
+}
+
+template <class KS>
+static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const double* tau, double* R, void* ws,
+                    int shard, int nshards, hipStream_t s) {
+  typedef typename KS::T T;
+  Carve cv(ws, p.bytes);
+  T* Bc = cv.take<T>(p.n_Bc);
+  T* Tp = cv.take<T>(p.n_Tp);
+  T* Tm = cv.take<T>(p.n_Tm);
+  T* Wp = cv.take<T>(p.n_W);
+  T* Wm = cv.take<T>(p.pm > 0 ? p.n_W : 0);
+  T* S = cv.take<T>(p.n_S);
+  T* A = cv.take<T>(p.n_A);
+
+  const double vv = static_cast<double>(p.v) * p.v, oo = static_cast<double>(p.o) * p.o;
+  const double pv = p.v * (p.v + 1.0) / 2, pvm = p.v * (p.v - 1.0) / 2;
+  RI_TRY(stage_inputs<KS>(p, B_vv, qs, rs, tau, Bc, Tp, Tm, s));
   for (long slab0 = 0; slab0 < p.nbp; slab0 += p.slab_bp) {
     if ((slab0 / p.slab_bp) % nshards != shard) continue;  // another shard's slab
     const long npairs = (p.nbp - slab0) < p.slab_bp ? (p.nbp - slab0) : p.slab_bp;
@@ -742,13 +762,13 @@ static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const d
       // per valid (a <= b): the v x v matrix (ac|bd) over all c, d, naux products each;
       // off-diagonal and diagonal ab block pairs in two launches
       ProfScope ps(s, KS::build, 2.0 * p.naux * vv * (le - ld));
-      KS::build_k(dim3(p.nbp * 4, npairs), s, Bc, p.naux_p, p.vp, slab0, p.slab_M, p.pm > 0 ? 1 : 0, Wp, Wm);
+      KS::build_k(dim3(p.nbp * 4, npairs), s, Bc, p.naux_p, p.vp, slab0, p.slab_M, p.pm > 0 ? 1 : 0, 0, Wp, Wm);
       RI_TRY(check_launch(KS::build));
     }
     if (ndiag > 0) {
       ProfScope ps(s, KS::build_diag, 2.0 * p.naux * vv * ld);
-      KS::build_diag_k(dim3(p.nbp * 4, ndiag), s, Bc, p.naux_p, p.vp, slab0, p.slab_M, p.pm > 0 ? 1 : 0, dy0, Wp,
-                       Wm);
+      KS::build_diag_k(dim3(p.nbp * 4, ndiag), s, Bc, p.naux_p, p.vp, slab0, p.slab_M, p.pm > 0 ? 1 : 0, dy0, 0,
+                       Wp, Wm);
       RI_TRY(check_launch(KS::build_diag));
     }
     {
@@ -782,6 +802,122 @@ static int run_typed(const Plan& p, int precision, const double* B_vv, long qs, 
 }
 
 static size_t esize_of(int precision) { return precision == RI_PREC_FP32 ? 4 : 8; }
+
+// ---------------------------------------------------------------- exchange symmetry
+// When the factors are symmetric in their two virtual indices (B[Q][a][c] = B[Q][c][a],
+// as for the bare integrals of eq. RIM), (ac|bd) has the full eight-fold symmetry of
+// real two-electron integrals, and with it V+-^{ab}_{cd} = V+-^{cd}_{ab}: over (ab) and
+// (cd) pairs the integral matrix is symmetric.  Slab [P0, P1) of ab block pairs then
+// builds only the cd block pairs >= P0 and uses each built element twice:
+//   S[ab]  = sum_{cd >= P0} W[cd][ab] T[cd]        contraction kernel, as in run_plan
+//   S2[cd] += sum_{ab in slab} W[cd][ab] T[ab]     for cd >= P1 (FP64 GEMM engine)
+// The cd < P0 part of a slab's own S arrived in S2 from the earlier slabs, and S2 is
+// unpacked into R once after the last slab.  With n equal slabs the build is
+// (1 + 1/n)/2 of run_plan's; the contraction FLOP are the same, split between the two
+// products.  The summation order differs from run_plan's, so the two agree to rounding.
+
+// Algorithmic FLOP of the exchange-symmetric form: the build and the two products,
+// summed over the plan's slabs.
+static void sym_flops(const Plan& p, double& build, double& contract) {
+  build = contract = 0.0;
+  for (long slab0 = 0; slab0 < p.nbp; slab0 += p.slab_bp) {
+    const long npairs = std::min(p.nbp - slab0, p.slab_bp), p1 = slab0 + npairs;
+    double le, lt, ld, ce, ct, cd, he, ht, hd;
+    count_pairs(p.v, slab0, npairs, le, lt, ld);      // ab pairs of the slab
+    count_pairs(p.v, slab0, p.nbp - slab0, ce, ct, cd);  // cd pairs built for it
+    count_pairs(p.v, p1, p.nbp - p1, he, ht, hd);        // cd pairs of its second product
+    build += 2.0 * p.naux * le * (2.0 * ct + (ce - ct));
+    contract += 2.0 * ((le * ce + le * he) * p.po + (lt * ct + lt * ht) * p.pm);
+  }
+}
+
+static int run_sym(const Plan& p, const double* B_vv, const double* tau, double* R, void* ws, hipStream_t s) {
+  typedef K64 KS;
+  typedef double T;
+  Carve cv(ws, p.bytes);
+  T* Bc = cv.take<T>(p.n_Bc);
+  T* Tp = cv.take<T>(p.n_Tp);
+  T* Tm = cv.take<T>(p.n_Tm);
+  T* Wp = cv.take<T>(p.n_W);
+  T* Wm = cv.take<T>(p.pm > 0 ? p.n_W : 0);
+  T* S = cv.take<T>(p.n_S);
+  T* A = cv.take<T>(p.n_A);
+  T* S2 = cv.take<T>(p.n_S2);
+  T* A2 = cv.take<T>(p.n_A2);
+  const double oo = static_cast<double>(p.o) * p.o;
+  RI_TRY(stage_inputs<KS>(p, B_vv, static_cast<long>(p.v) * p.v, p.v, tau, Bc, Tp, Tm, s));
+  GemmArena arena;
+  arena.s = s;
+  long first_p1 = -1;  // first row pair of S2 written (by the first slab's second product)
+  for (long slab0 = 0; slab0 < p.nbp; slab0 += p.slab_bp) {
+    const long npairs = std::min(p.nbp - slab0, p.slab_bp), p1 = slab0 + npairs;
+    const long M = npairs * 256;
+    const long K1 = p.K - slab0 * 256;  // cd slots from the slab's first pair on
+    double le, lt, ld, ce, ct, cd;
+    count_pairs(p.v, slab0, npairs, le, lt, ld);
+    count_pairs(p.v, slab0, p.nbp - slab0, ce, ct, cd);
+    int dy0, ndiag;
+    diag_pairs(slab0, npairs, dy0, ndiag);
+    const unsigned gx = static_cast<unsigned>((p.nbp - slab0) * 4);
+    const double per_ab = 2.0 * p.naux * (2.0 * ct + (ce - ct));
+    {
+      ProfScope ps(s, KS::build, per_ab * (le - ld));
+      KS::build_k(dim3(gx, npairs), s, Bc, p.naux_p, p.vp, slab0, p.slab_M, p.pm > 0 ? 1 : 0, slab0, Wp, Wm);
+      RI_TRY(check_launch(KS::build));
+    }
+    if (ndiag > 0) {
+      ProfScope ps(s, KS::build_diag, per_ab * ld);
+      KS::build_diag_k(dim3(gx, ndiag), s, Bc, p.naux_p, p.vp, slab0, p.slab_M, p.pm > 0 ? 1 : 0, dy0, slab0, Wp,
+                       Wm);
+      RI_TRY(check_launch(KS::build_diag));
+    }
+    const size_t w0 = static_cast<size_t>(slab0) * 256 * p.slab_M;  // row slab0*256 of W
+    long kzp = 0, kzm = 0;
+    const int zp = contract_splits(p.NP, p.ntw_p, M, K1, kzp);
+    const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, K1, kzm) : 1;
+    {
+      ProfScope ps(s, KS::contract, 2.0 * (le * ce * p.po + lt * ct * p.pm));
+      launch_contract<KS>(p.ntw_p, Wp + w0, Tp + static_cast<size_t>(slab0) * 256 * p.NP, K1, p.slab_M, M, p.NP, S,
+                          zp, kzp, s);
+      RI_TRY(check_launch(KS::contract));
+      if (p.pm > 0) {
+        launch_contract<KS>(p.ntw_m, Wm + w0, Tm + static_cast<size_t>(slab0) * 256 * p.NM, K1, p.slab_M, M, p.NM,
+                            A, zm, kzm, s);
+        RI_TRY(check_launch(KS::contract));
+      }
+    }
+    {
+      ProfScope ps(s, KS::unpack, 0.0, 16.0 * oo * (le + lt));
+      unpack_kernel<T><<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R, zp,
+                                                                        M * p.NP, zm, M * p.NM);
+      RI_TRY(check_launch(KS::unpack));
+    }
+    if (p1 < p.nbp) {  // second product: rows cd >= P1 of W against the slab's own T rows
+      const long rows = (p.nbp - p1) * 256;
+      const double beta = first_p1 < 0 ? 0.0 : 1.0;
+      if (first_p1 < 0) first_p1 = p1;
+      const size_t wr = static_cast<size_t>(p1) * 256 * p.slab_M;
+      RI_TRY(einsum("km,mn->kn", 1.0, Tensor(Wp + wr, {rows, M}, {p.slab_M, 1}),
+                    Tensor(Tp + static_cast<size_t>(slab0) * 256 * p.NP, {M, p.NP}), beta,
+                    Tensor(S2 + static_cast<size_t>(p1) * 256 * p.NP, {rows, p.NP}), arena, s));
+      if (p.pm > 0)
+        RI_TRY(einsum("km,mn->kn", 1.0, Tensor(Wm + wr, {rows, M}, {p.slab_M, 1}),
+                      Tensor(Tm + static_cast<size_t>(slab0) * 256 * p.NM, {M, p.NM}), beta,
+                      Tensor(A2 + static_cast<size_t>(p1) * 256 * p.NM, {rows, p.NM}), arena, s));
+    }
+  }
+  if (first_p1 >= 0) {
+    const long n2 = p.nbp - first_p1;
+    double le, lt, ld;
+    count_pairs(p.v, first_p1, n2, le, lt, ld);
+    ProfScope ps(s, KS::unpack, 0.0, 16.0 * oo * (le + lt));
+    unpack_kernel<T><<<dim3(n2, (p.po + NG - 1) / NG), 256, 0, s>>>(
+        S2 + static_cast<size_t>(first_p1) * 256 * p.NP, A2 + static_cast<size_t>(first_p1) * 256 * p.NM, p.NP,
+        p.NM, p.o, p.v, first_p1, R, 1, 0, 1, 0);
+    RI_TRY(check_launch(KS::unpack));
+  }
+  return RI_OK;
+}
 
 // ---------------------------------------------------------------- pair symmetry
 // The ladder uses only the pair-symmetric part of tau (tau^{cd}_{ij} = tau^{dc}_{ji},
@@ -836,11 +972,34 @@ __global__ __launch_bounds__(256) void pair_asym_final(const double* __restrict_
     out[1] = amax;
   }
 }
-int pair_asymmetry(const double* tau, int o, int v, double* host2, hipStream_t s) {
+// The same for factors: out = {max |B[q][a][c] - B[q][c][a]|, max |B|}.
+__global__ __launch_bounds__(256) void factor_asym_partial(const double* __restrict__ B, int naux, int v,
+                                                           double* part) {
+  __shared__ double sh[512];
+  const long vv = static_cast<long>(v) * v, n = static_cast<long>(naux) * vv;
+  double asym = 0.0, amax = 0.0;
+  for (long x = static_cast<long>(blockIdx.x) * 256 + threadIdx.x; x < n; x += static_cast<long>(gridDim.x) * 256) {
+    const long q = x / vv, ac = x - q * vv;
+    const int a = static_cast<int>(ac / v), c = static_cast<int>(ac - static_cast<long>(a) * v);
+    const double t = B[x];
+    const double m = B[q * vv + static_cast<long>(c) * v + a];
+    asym = nan_max(asym, fabs(t - m));
+    amax = nan_max(amax, fabs(t));
+  }
+  block_max2(asym, amax, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = asym;
+    part[2 * blockIdx.x + 1] = amax;
+  }
+}
+// Runs a partial kernel (launched by `partial` into ASYM_BLOCKS pairs) and the final
+// reduction; copies the two maxima to host2 and synchronises the stream.
+template <class F>
+static int max_pair(F&& partial, double* host2, hipStream_t s) {
   void* buf = nullptr;
   RI_TRY(dev_alloc(&buf, (2 * ASYM_BLOCKS + 2) * sizeof(double), s));
   double* part = static_cast<double*>(buf);
-  pair_asym_partial<<<ASYM_BLOCKS, 256, 0, s>>>(tau, o, v, part);
+  partial(part);
   pair_asym_final<<<1, 256, 0, s>>>(part, part + 2 * ASYM_BLOCKS);
   int rc = check_launch("pair_asym");
   if (rc == RI_OK) rc = check_hip(hipMemcpyAsync(host2, part + 2 * ASYM_BLOCKS, 2 * sizeof(double),
@@ -848,6 +1007,13 @@ int pair_asymmetry(const double* tau, int o, int v, double* host2, hipStream_t s
   if (rc == RI_OK) rc = check_hip(hipStreamSynchronize(s), "pair_asym sync");
   dev_free(buf, s);
   return rc;
+}
+int pair_asymmetry(const double* tau, int o, int v, double* host2, hipStream_t s) {
+  return max_pair([&](double* part) { pair_asym_partial<<<ASYM_BLOCKS, 256, 0, s>>>(tau, o, v, part); }, host2, s);
+}
+int factor_asymmetry(const double* B, int naux, int v, double* host2, hipStream_t s) {
+  return max_pair([&](double* part) { factor_asym_partial<<<ASYM_BLOCKS, 256, 0, s>>>(B, naux, v, part); }, host2,
+                  s);
 }
 // RI_PPL_CHECK_TAU set (and not "0"): the ladder first checks that tau is
 // pair-symmetric to 1e-12 of its largest element and rejects it otherwise.
@@ -954,6 +1120,52 @@ int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, dou
 
 int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream) {
   return ri_ppl_ex(B_vv, tau, o, v, naux, R, RI_PREC_FP64, nullptr, 0, stream);
+}
+
+int ri_ppl_sym(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream) {
+  clear_error();
+  if (!B_vv || !tau || !R) {
+    set_error("ri_ppl_sym: null pointer argument");
+    return RI_E_ARG;
+  }
+  ppl::Plan p;
+  if (!ppl::make_plan(o, v, naux, 8, p, true)) {
+    set_error("ri_ppl_sym: invalid sizes o=%d v=%d naux=%d", o, v, naux);
+    return RI_E_ARG;
+  }
+  const size_t nB = static_cast<size_t>(naux) * v * v * sizeof(double);
+  const size_t nT = static_cast<size_t>(o) * o * v * v * sizeof(double);
+  if (overlaps(R, nT, B_vv, nB) || overlaps(R, nT, tau, nT)) {
+    set_error("ri_ppl_sym: R overlaps an input");
+    return RI_E_ALIAS;
+  }
+  if ((reinterpret_cast<uintptr_t>(B_vv) | reinterpret_cast<uintptr_t>(tau) |
+       reinterpret_cast<uintptr_t>(R)) & 7) {
+    set_error("ri_ppl_sym: arrays must be 8-byte aligned");
+    return RI_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RI_TRY(ppl::check_tau_if_asked(tau, o, v, s));
+  double r[2];
+  RI_TRY(ppl::factor_asymmetry(B_vv, naux, v, r, s));
+  if (!(r[0] <= 1e-12 * r[1])) {
+    set_error("ri_ppl_sym: B_vv is not symmetric in its virtual indices: max |B_ac - B_ca| = %.3e, max |B| = %.3e",
+              r[0], r[1]);
+    return RI_E_ARG;
+  }
+  void* buf = nullptr;
+  RI_TRY(dev_alloc(&buf, p.bytes, s));
+  const int rc = ppl::run_sym(p, B_vv, tau, R, buf, s);
+  dev_free(buf, s);
+  return rc;
+}
+
+double ri_ppl_sym_flops(int o, int v, int naux) {
+  ppl::Plan p;
+  if (!ppl::make_plan(o, v, naux, 8, p, true)) return 0.0;
+  double build, contract;
+  ppl::sym_flops(p, build, contract);
+  return build + contract;
 }
 
 int ri_tau_pair_asymmetry(const double* tau, int o, int v, double* result, void* stream) {

@@ -72,6 +72,25 @@ def ppl_paper(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, stream=Non
     return R
 
 
+def ppl_sym(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, stream=None) -> torch.Tensor:
+    """The same sum for factors symmetric in their two virtual indices, using the
+    exchange symmetry of the integral matrix to build about half of it (ri_ppl_sym),
+    FP64."""
+    naux, v = B_vv.shape[0], B_vv.shape[1]
+    o = tau.shape[0]
+    _need(B_vv, "B_vv", (naux, v, v))
+    _need(tau, "tau", (o, o, v, v))
+    _need(R, "R", (o, o, v, v))
+    _lib.check(_lib.lib().ri_ppl_sym(B_vv.data_ptr(), tau.data_ptr(), o, v, naux, R.data_ptr(), _stream(stream)),
+               "ri_ppl_sym")
+    return R
+
+
+def sym_flops(o: int, v: int, naux: int) -> float:
+    """Algorithmic FLOP of ri_ppl_sym over its slab schedule."""
+    return float(_lib.lib().ri_ppl_sym_flops(o, v, naux))
+
+
 def paper_flops(o: int, v: int, naux: int) -> float:
     """FLOP of ri_ppl_paper: 2 Naux v^4 (full build) + v^4 o(o+1) (i <= j contraction)."""
     return float(_lib.lib().ri_ppl_paper_flops(o, v, naux))

@@ -78,3 +78,24 @@ def test_triples_argument_checks():
     assert L.ri_ccsd_triples(None, 8, 8, ctypes.byref(e), None) == 1
     assert L.ri_ccsd_triples_flops(2, 3) == 2 * 3 * 4 * (2.0 * 81 + 2.0 * 27 * 2)
     assert L.ri_ccsd_triples_flops(0, 3) == 0.0
+
+
+def test_exchange_symmetric_form_flops_and_argument_checks(monkeypatch):
+    from paper_1810_08142_amd import _lib
+    L = _lib.lib()
+    assert L.ri_ppl_sym(None, None, 2, 3, 4, None, None) == 1
+    assert L.ri_ppl_sym(8, 16, 0, 3, 4, 24, None) == 1
+    assert L.ri_ppl_sym(4096, 8192, 2, 3, 4, 8192, None) == 2
+    assert L.ri_ppl_sym_flops(0, 3, 4) == 0.0
+    # one slab: nothing is built twice or skipped, the FLOP are those of ri_ppl
+    monkeypatch.setenv("RI_PPL_SYM_SLABS", "1")
+    assert L.ri_ppl_sym_flops(3, 40, 50) == L.ri_ppl_flops(3, 40, 50)
+    # n slabs at o=16 v=256 naux=768: the build falls to about (1 + 1/n)/2, the
+    # contraction is unchanged
+    o, v, n = 16, 256, 768
+    build = float(n * v**3 * (v + 1))
+    contract = L.ri_ppl_flops(o, v, n) - build
+    for slabs in (2, 8, 136):
+        monkeypatch.setenv("RI_PPL_SYM_SLABS", str(slabs))
+        got = L.ri_ppl_sym_flops(o, v, n) - contract
+        assert build / 2 < got <= build * (1 + 1 / slabs) / 2 * 1.02, (slabs, got / build)

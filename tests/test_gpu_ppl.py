@@ -327,3 +327,61 @@ def test_paper_arrangement_chunks_do_not_change_result(monkeypatch):
         ppl.ppl_paper(B, T, R)
         outs.append(host(R))
     assert rel_max(outs[1], outs[0]) <= 1e-13 and rel_max(outs[2], outs[0]) <= 1e-13
+
+
+@pytest.mark.parametrize("o,v,naux,slabs,large", [
+    (1, 3, 2, 8, 0),        # one block pair: a single slab, no second product
+    (2, 17, 7, 8, 0),       # three block pairs, one per slab
+    (1, 50, 20, 3, 0),      # o = 1 (no antisymmetric part) over several slabs
+    (3, 33, 20, 3, 1),      # ragged slabs, second product on the large-tile GEMM kernel
+    (4, 40, 37, 8, 0),
+    (2, 50, 130, 4, 1),
+    (3, 70, 24, 1000, 0),   # one block pair per slab (15 slabs)
+    (5, 64, 40, 2, 0),      # v a multiple of 16, two slabs
+])
+def test_exchange_symmetric_form_matches_oracle(o, v, naux, slabs, large, monkeypatch):
+    """ri_ppl_sym (half the build through the (ab) <-> (cd) exchange symmetry) gives the
+    oracle's ladder to 1e-11 and ri_ppl's to rounding, for any slab schedule."""
+    import torch
+    ppl = _ppl()
+    print(f"ppl_sym o={o} v={v} naux={naux} slabs={slabs} large={large}", flush=True)
+    monkeypatch.setenv("RI_PPL_SYM_SLABS", str(slabs))
+    if large:
+        monkeypatch.setenv("RI_GEMM_LARGE_MIN_TILES", "1")
+    s = draw_system(o, v, naux, seed=o * 100 + v + 7)
+    B = np.ascontiguousarray(s.B_vv)
+    T = draw_pair_symmetric(o, v, 11 + v, 0.01)
+    R0 = draw_matrix((o, o, v, v), 13)
+    ref = native.ppl(B, T, R0.copy())
+    R = dev(R0)
+    ppl.ppl_sym(dev(B), dev(T), R)
+    got = host(R)
+    assert rel_max(got - R0, ref - R0) <= TOL and rel_fro(got - R0, ref - R0) <= TOL
+    Rt = _gpu_ladder(B, T, R0)
+    assert rel_max(got - R0, Rt - R0) <= TOL
+    torch.cuda.synchronize()
+
+
+def test_exchange_symmetric_form_checks_its_factors_and_arguments():
+    """Dressed (non-symmetric) factors are rejected with R untouched; a symmetric
+    B passes; null and overlapping arguments give their status codes."""
+    import torch
+    from paper_1810_08142_amd import _lib
+    ppl = _ppl()
+    o, v, naux = 3, 21, 11
+    s = draw_system(o, v, naux, seed=601, scale=0.2)
+    t1 = draw_matrix((o, v), 602, 0.1)
+    Bd = dev(np.ascontiguousarray(oc.dress(s.B, t1)[:, o:, o:]))
+    T = dev(draw_pair_symmetric(o, v, 603))
+    R = torch.full((o, o, v, v), 0.5, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.RIError) as ei:
+        ppl.ppl_sym(Bd, T, R)
+    assert ei.value.status == 1 and "not symmetric" in str(ei.value)
+    assert bool((R == 0.5).all())
+    B = dev(np.ascontiguousarray(s.B_vv))
+    ppl.ppl_sym(B, T, R)
+    assert not bool((R == 0.5).all())
+    L = _lib.lib()
+    assert L.ri_ppl_sym(None, T.data_ptr(), o, v, naux, R.data_ptr(), None) == 1
+    assert L.ri_ppl_sym(B.data_ptr(), T.data_ptr(), o, v, naux, T.data_ptr(), None) == 2
+    torch.cuda.synchronize()
