@@ -267,7 +267,8 @@ int ri_ccsd_triples(const ri_system* sys, const double* t1, const double* t2, do
 /* The same with a choice of arithmetic for the term GEMMs: RI_PREC_FP64, or RI_PREC_FP32
  * (operands rounded to FP32, FP32 MFMA with FP32 accumulation over the summed index of
  * v + o, where the GEMM takes its 128 x 128 tile kernel; W, V and the energy sum stay
- * FP64).  The FP32 error of E_(T) is ~1e-7 of its size.  RI_E_ARG for other values. */
+ * FP64).  The FP32 error of E_(T) was 1e-8 of its size at o = 24, v = 384.  RI_E_ARG
+ * for other precision values. */
 int ri_ccsd_triples_ex(const ri_system* sys, const double* t1, const double* t2, int precision, double* e_t,
                        void* stream);
 double ri_ccsd_triples_flops(int o, int v);
