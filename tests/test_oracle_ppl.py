@@ -182,3 +182,46 @@ def test_symmetric_antisymmetric_split_equals_full_sum():
                     R[i, j, a, b] = S + A
     ref = native.ppl(B, tau)
     assert np.abs(R - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_pair_exchange_symmetry_needs_symmetric_factors():
+    """The premise of the exchange-symmetric ladder: with B^Q_ac = B^Q_ca the integral
+    matrix V+-[(ab)][(cd)] = (ac|bd) +- (ad|bc) is symmetric under (ab) <-> (cd), so
+    summing over the pairs (cd) >= (ab) and using each off-diagonal element twice gives
+    the ladder; t1-dressed factors break the symmetry."""
+    o, v, naux = 2, 6, 5
+    s = draw_system(o, v, naux, seed=21)
+    B = np.ascontiguousarray(s.B_vv)
+    g = oc.eri(B, B)                                   # g[a][c][b][d] = (ac|bd)
+    Vp = np.einsum("acbd->abcd", g) + np.einsum("adbc->abcd", g)  # (ac|bd) + (ad|bc)
+    Vm = np.einsum("acbd->abcd", g) - np.einsum("adbc->abcd", g)
+    for V in (Vp, Vm):
+        np.testing.assert_allclose(V, V.transpose(2, 3, 0, 1), rtol=0, atol=1e-13 * np.abs(V).max())
+    # the ladder from the (cd) >= (ab) half of the pair-pair matrix, each element used twice
+    tau = draw_pair_symmetric(o, v, 22)
+    pairs = [(a, b) for b in range(v) for a in range(b + 1)]   # a <= b, numbered in order
+    tp = 0.5 * (tau + tau.transpose(0, 1, 3, 2))
+    tm = 0.5 * (tau - tau.transpose(0, 1, 3, 2))
+    S = np.zeros((o, o, len(pairs)))
+    A = np.zeros((o, o, len(pairs)))
+    for x, (a, b) in enumerate(pairs):
+        for y in range(x, len(pairs)):
+            c, d = pairs[y]
+            sg = 0.5 if c == d else 1.0
+            sa = 0.5 if a == b else 1.0
+            S[:, :, x] += sg * Vp[a, b, c, d] * tp[:, :, c, d]
+            A[:, :, x] += Vm[a, b, c, d] * tm[:, :, c, d]
+            if y > x:
+                S[:, :, y] += sa * Vp[a, b, c, d] * tp[:, :, a, b]
+                A[:, :, y] += Vm[a, b, c, d] * tm[:, :, a, b]
+    R = np.zeros((o, o, v, v))
+    for x, (a, b) in enumerate(pairs):
+        R[:, :, a, b] = S[:, :, x] + A[:, :, x]
+        R[:, :, b, a] = S[:, :, x] - A[:, :, x]
+    ref = native.ppl(B, tau)
+    np.testing.assert_allclose(R, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    # dressed factors: the exchange symmetry fails
+    Bd = np.ascontiguousarray(oc.dress(s.B, draw_matrix((o, v), 23, 0.1))[:, o:, o:])
+    gd = oc.eri(Bd, Bd)
+    Vd = np.einsum("acbd->abcd", gd) + np.einsum("adbc->abcd", gd)
+    assert np.abs(Vd - Vd.transpose(2, 3, 0, 1)).max() > 1e-3 * np.abs(Vd).max()
