@@ -1,4 +1,5 @@
-// Perturbative triples energy E_(T) of closed-shell CCSD(T) (Sec. II.A), FP64.
+// Perturbative triples energy E_(T) of closed-shell CCSD(T) (Sec. II.A): FP64, with an
+// FP32 option for the term GEMMs.
 //
 //   E_(T) = sum_{ijk} sum_{abc} (4 W^{abc}_{ijk} + W^{bca}_{ijk} + W^{cab}_{ijk})
 //                               (V^{abc}_{ijk} - V^{cba}_{ijk}) / (3 D^{abc}_{ijk}),
@@ -15,7 +16,7 @@
 // so the energy kernel evaluates it for each distinct ordering (i', j', k') from the
 // one W and V, reading them through permuted tiles.
 //
-// Per triplet: six GEMMs on the library's FP64 MFMA engine, one per term of P, each
+// Per triplet: six GEMMs on the library's MFMA engine (FP64 or FP32), one per term of P, each
 // writing its term in its own natural layout (contiguous output rows; the o-sized sum
 // of a term rides along as extra columns of the summed index), a tiled kernel
 // symmetrises the six into W and forms V = W + the t1 terms, and a tiled kernel sums
