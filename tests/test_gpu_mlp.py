@@ -56,6 +56,37 @@ def test_adam_step_matches_oracle():
     assert np.abs(new - ref)[clear].max() <= 1e-5
 
 
+def test_adam_steps_follow_the_oracle_trajectory():
+    """Five consecutive ri_mlp_train_step calls on one batch against the oracle's own
+    FP64 trajectory (its gradient, then its Adam step with the step count t = 1..5):
+    after every step the parameters agree to 1e-5, so the library's step counter
+    reaches the bias corrections as the oracle's does.  Parameters whose gradient is
+    within FP32 noise of zero at some step are left out (there Adam's normalised step
+    may take either sign)."""
+    hidden, layers, n, lr = 32, 2, 300, 1e-3
+    net, theta = _net(8, hidden, layers, seed=19)
+    X = draw_matrix((n, 8), 17).astype(np.float32)
+    Y = draw_matrix(n, 18).astype(np.float32)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    Xd, Yd = dev(X), dev(Y)
+    ref, m, v = theta.copy(), np.zeros_like(theta), np.zeros_like(theta)
+    clear = np.ones(theta.size, dtype=bool)
+    worst = 0.0
+    for t in range(1, 6):
+        loss = net.train_step(Xd, Yd, lr)
+        L, g = om.gradient(ref, X64, Y64, 8, hidden, layers)
+        ref, m, v = om.adam_step(ref, g, m, v, t, lr)
+        clear &= np.abs(g) > 1e-3 * np.abs(g).max()
+        got = net.get_params().astype(np.float64)
+        assert abs(loss - L) <= 1e-4 * L
+        err = float(np.abs(got - ref)[clear].max())
+        worst = max(worst, err)
+        print(f"adam step {t}: max |theta_gpu - theta_oracle| = {err:.2e} over {int(clear.sum())} parameters",
+              flush=True)
+        assert err <= 1e-5
+    assert clear.sum() > 0.5 * theta.size
+
+
 def test_features_match_oracle():
     from paper_1810_08142_amd import mlp
     o, v, naux = 3, 13, 20

@@ -126,30 +126,6 @@ def test_build_tau():
     assert bool(np.all(np.abs(got - ref) <= bound))
 
 
-def test_c2_full_size_sampled():
-    """c2 (o=16, v=256, naux=768) in the benchmark's launch configuration; tau is the
-    oracle's MP2 t2 + t1 (x) t1.  The oracle recomputes 48 sampled (a, b) pairs."""
-    import torch
-    c = CONFIGS["c2"]
-    o, v, naux = c["o"], c["v"], c["naux"]
-    print("c2: drawing system", flush=True)
-    s = draw_system(o, v, naux, seed=c["seed"])
-    _, t2, _ = oc.mp2(s.B, s.eps, o)
-    tau = oc.make_tau(s.t1, t2)
-    B_vv = s.B_vv
-    print("c2: GPU ladder", flush=True)
-    R = _gpu_ladder(B_vv, tau)
-    rng = np.random.default_rng(7)
-    pairs = [(int(a), int(b)) for a, b in rng.integers(0, v, size=(44, 2))] + [(0, 0), (v - 1, v - 1), (0, v - 1), (v - 1, 0)]
-    print("c2: oracle sample", flush=True)
-    ref = native.ppl_pairs(B_vv, tau, pairs)
-    got = np.stack([R[:, :, a, b] for a, b in pairs])
-    scale = np.abs(ref).max()
-    assert np.abs(got - ref).max() / scale <= TOL
-    assert np.array_equal(R, R.transpose(1, 0, 3, 2))
-    assert np.isfinite(R).all()
-
-
 @pytest.mark.slow
 @pytest.mark.timeout(1200)
 def test_c4_full_size_sampled_fp64_and_mixed():

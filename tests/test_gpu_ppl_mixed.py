@@ -92,24 +92,6 @@ def test_mixed_slabs_do_not_change_result(precision):
     assert np.array_equal(R1, R2)
 
 
-def test_mixed_c2_full_size_sampled():
-    c = CONFIGS["c2"]
-    o, v, naux = c["o"], c["v"], c["naux"]
-    s = draw_system(o, v, naux, seed=c["seed"])
-    _, t2, _ = oc.mp2(s.B, s.eps, o)
-    tau = oc.make_tau(s.t1, t2)
-    rng = np.random.default_rng(8)
-    pairs = [(int(a), int(b)) for a, b in rng.integers(0, v, size=(24, 2))] + [(0, 0), (v - 1, 0)]
-    ref = native.ppl_pairs(s.B_vv, tau, pairs)
-    bound = EPS * native.ppl_pairs(np.abs(s.B_vv), np.abs(tau), pairs)
-    for precision in PRECS:
-        R = _ladder(s.B_vv, tau, precision)
-        got = np.stack([R[:, :, a, b] for a, b in pairs])
-        print(f"c2 {precision} max rel err", float(np.abs(got - ref).max() / np.abs(ref).max()), flush=True)
-        assert bool(np.all(np.abs(got - ref) <= bound))
-        assert np.array_equal(R, R.transpose(1, 0, 3, 2))
-
-
 @pytest.mark.parametrize("precision", PRECS)
 def test_ccsd_with_mixed_ladder_energy_within_microhartree(precision):
     from paper_1810_08142_amd import ccsd

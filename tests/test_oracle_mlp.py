@@ -1,6 +1,7 @@
 """Pins of the CPU oracle of the learned guess: a hand-worked forward pass,
-central finite differences of the loss, the exact-fit stationary point, the
-closed form of Adam's first step, and the symmetry of the features."""
+central finite differences of the loss, the exact-fit stationary point, closed
+forms of Adam's steps (the first step, a constant gradient over several steps, a
+single kick decaying over later steps), and the symmetry of the features."""
 import math
 import os
 
@@ -54,6 +55,42 @@ def test_adam_first_step_closed_form():
     new, m, v = mlp.adam_step(theta, g, np.zeros(3), np.zeros(3), 1, lr=0.01)
     # bias-corrected moments of step one are g and g^2
     np.testing.assert_allclose(new, theta - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_adam_constant_gradient_moves_by_the_same_step_every_time():
+    # With the same gradient g at every step the moments are m_t = (1 - b1^t) g and
+    # v_t = (1 - b2^t) g^2 (geometric sums), so the bias-corrected update is
+    # lr g / (|g| + eps) at every t.  A bias correction with a wrong step-count
+    # dependence (for example 1 - b1 t) moves differently from t = 2 on.
+    theta0 = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([0.3, -4.0, 1e-3, 2.5e-6])
+    lr = 0.01
+    step = lr * g / (np.abs(g) + 1e-8)
+    theta, m, v = theta0.copy(), np.zeros(4), np.zeros(4)
+    for t in range(1, 8):
+        new, m, v = mlp.adam_step(theta, g, m, v, t, lr=lr)
+        np.testing.assert_allclose(theta - new, step, rtol=1e-12, atol=1e-17)
+        theta = new
+    np.testing.assert_allclose(theta, theta0 - 7 * step, rtol=1e-12, atol=1e-15)
+
+
+def test_adam_single_kick_decays_geometrically():
+    # Gradient g at step 1 and zero afterwards: m_t = b1^(t-1) (1 - b1) g and
+    # v_t = b2^(t-1) (1 - b2) g^2, so step t moves theta by
+    #   lr * [b1^(t-1) (1 - b1) / (1 - b1^t)] g
+    #      / (sqrt(b2^(t-1) (1 - b2) / (1 - b2^t)) |g| + eps).
+    # This fixes which of beta and 1 - beta weights the old moment and that the
+    # square root is taken of the second moment only.
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 0.05
+    g1 = np.array([0.7, -1.5, 2.0])
+    theta, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 7):
+        g = g1 if t == 1 else np.zeros(3)
+        new, m, v = mlp.adam_step(theta, g, m, v, t, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        mhat = b1 ** (t - 1) * (1 - b1) / (1 - b1 ** t) * g1
+        shat = math.sqrt(b2 ** (t - 1) * (1 - b2) / (1 - b2 ** t)) * np.abs(g1)
+        np.testing.assert_allclose(theta - new, lr * mhat / (shat + eps), rtol=1e-12, atol=0)
+        theta = new
 
 
 def test_features_pair_symmetric_and_defined():
