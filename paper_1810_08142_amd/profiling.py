@@ -130,7 +130,10 @@ def mfma(kernel: str, pmc_csv: str, algo_flops: float, peak_tflops: float, sourc
     busy = sum(r.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for r in rows) / n
     active = sum(r.get("GRBM_GUI_ACTIVE", 0.0) for r in rows) / n
     executed = mops * 512.0
-    return dict(kernel=kernel, source_hash=source_hash, launches=n, counters_per_launch={k: v for k, v in rows[0].items()},
+    keys = sorted({k for r in rows for k in r})
+    mean = {k: sum(r.get(k, 0.0) for r in rows) / n for k in keys}  # "ns" included: the mean dispatch time
+    return dict(kernel=kernel, source_hash=source_hash, launches=n, counters_mean_per_launch=mean,
+                counters_first_dispatch={k: v for k, v in rows[0].items()},
                 executed_mfma_flop_per_launch=executed, algorithmic_flop_per_launch=algo_flops,
                 algorithmic_share=algo_flops / executed if executed else None,
                 executed_tflops=executed / (ns * 1e-9) / 1e12 if ns else None,
