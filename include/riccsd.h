@@ -88,6 +88,26 @@ int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double
 int ri_ppl_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R,
               int precision, void* ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free ladder, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * computation, arguments, error codes and error bound as ri_ppl_ex with ws == NULL,
+ * but the workspace is a fixed device array inside the library,
+ * RI_PPL_NOALLOC_MAX_BYTES (64 MiB) on every device that loads it, held until the
+ * process ends; the call allocates and frees nothing (the per-kernel event profiler
+ * stays off for it).  The slab of (ab) block pairs is the widest whose workspace fits
+ * that array, so results can differ from ri_ppl_ex in rounding only (the summation
+ * order of the contraction's k splits).  Sizes whose one-block-pair plan does not fit
+ * return RI_E_NOMEM and change nothing; as a guide, the FP64 workspace is about
+ * 8 vp^2 naux_p + 2 * 8 K (o^2/2 + 256) bytes with vp = v rounded up to 16,
+ * naux_p = naux rounded up to 16 and K = 128 (vp/16)(vp/16 + 1), so o = 8, v = 96,
+ * naux = 288 fits in FP64 and o = 8, v = 128, naux = 384 only in FP32 and bf16x3.
+ * Every call on one device shares that device's array: calls that overlap on one
+ * device (several streams or host threads) race, and the caller must serialise them.
+ * `stream` must belong to the current device (RI_E_ARG otherwise). */
+#define RI_PPL_NOALLOC_MAX_BYTES (64u << 20)
+int ri_ppl_noalloc(const double* B_vv, const double* tau, int o, int v, int naux, double* R, int precision,
+                   void* stream);
+
 /* One shard of a ladder call split over several devices: the split of the virtual
  * index a across domains of Sec. II.D, at the granularity of the (ab) block-pair
  * slabs.  Shard k of n (0 <= k < n) builds and contracts the slabs k, k + n,

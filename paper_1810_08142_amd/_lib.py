@@ -62,6 +62,7 @@ _SIGS = [
     ("ri_ppl_paper", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _dp]),
     ("ri_ppl_paper_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_sym", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _dp]),
+    ("ri_ppl_noalloc", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _c.c_int, _dp]),
     ("ri_ppl_sym_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_workspace_bytes", _c.c_size_t, [_c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),

@@ -78,9 +78,14 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
+thread_local bool g_prof_suppressed = false;
 }  // namespace
 
+ProfSuppress::ProfSuppress() : prev_(g_prof_suppressed) { g_prof_suppressed = true; }
+ProfSuppress::~ProfSuppress() { g_prof_suppressed = prev_; }
+
 ProfScope::ProfScope(hipStream_t s, const char* name, double flops, double bytes) : s_(s) {
+  if (g_prof_suppressed) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on) return;
   ProfRec r{name, nullptr, nullptr, flops, bytes};

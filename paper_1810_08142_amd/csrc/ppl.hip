@@ -577,9 +577,30 @@ static long max_split_rows(const Plan& p, int ncol, int ntw) {
   return best;
 }
 
+// Element counts and total bytes of plan p for its slab width p.slab_bp.
+static void size_plan(Plan& p, bool sym) {
+  p.slab_M = p.slab_bp * 256;
+  p.n_Bc = static_cast<size_t>(p.vp) * p.naux_p * p.vp;
+  p.n_Tp = static_cast<size_t>(p.K) * p.NP;
+  p.n_Tm = static_cast<size_t>(p.K) * p.NM;
+  p.n_W = static_cast<size_t>(p.K) * p.slab_M;
+  p.zrows_p = max_split_rows(p, p.NP, p.ntw_p);
+  p.zrows_m = max_split_rows(p, p.NM, p.ntw_m);
+  p.n_S = static_cast<size_t>(p.zrows_p) * p.NP;
+  p.n_A = static_cast<size_t>(p.zrows_m) * p.NM;
+  p.n_S2 = sym ? static_cast<size_t>(p.K) * p.NP : 0;
+  p.n_A2 = sym ? static_cast<size_t>(p.K) * p.NM : 0;
+  size_t b = 0;
+  for (size_t n : {p.n_Bc, p.n_Tp, p.n_Tm, p.n_W, p.pm > 0 ? p.n_W : 0, p.n_S, p.n_A, p.n_S2, p.n_A2})
+    b = round_up(b, 256) + n * p.esize;
+  p.bytes = round_up(b, 256);
+}
+
 // sym: the plan of the exchange-symmetric form (smaller slabs, second-product
-// accumulators); see run_sym.
-static bool make_plan(int o, int v, int naux, size_t esize, Plan& p, bool sym = false) {
+// accumulators); see run_sym.  fit_bytes > 0: the widest slab whose whole workspace
+// fits in fit_bytes (false if not even a one-block-pair slab fits), instead of the
+// W budget RI_PPL_W_BYTES.
+static bool make_plan(int o, int v, int naux, size_t esize, Plan& p, bool sym = false, size_t fit_bytes = 0) {
   if (o <= 0 || v <= 0 || naux <= 0) return false;
   if (o > 4096 || v > 65536 || naux > (1 << 24)) return false;
   p.o = o;
@@ -602,27 +623,28 @@ static bool make_plan(int o, int v, int naux, size_t esize, Plan& p, bool sym = 
   bp = bp < 1 ? 1 : bp;
   bp = bp > p.nbp ? p.nbp : bp;
   bp = bp > 65535 ? 65535 : bp;
+  if (fit_bytes > 0) bp = std::min(p.nbp, 65535L);
   const long cap = env_long("RI_PPL_SLAB_PAIRS", bp);
   p.slab_bp = cap < bp ? cap : bp;
   if (sym) {  // at least RI_PPL_SYM_SLABS (8) slabs: the build is (1 + 1/slabs)/2 of the full one
     const long ns = env_long("RI_PPL_SYM_SLABS", 8);
     p.slab_bp = std::min(p.slab_bp, (p.nbp + ns - 1) / ns);
   }
-  p.slab_M = p.slab_bp * 256;
-  p.n_Bc = static_cast<size_t>(p.vp) * p.naux_p * p.vp;
-  p.n_Tp = static_cast<size_t>(p.K) * p.NP;
-  p.n_Tm = static_cast<size_t>(p.K) * p.NM;
-  p.n_W = static_cast<size_t>(p.K) * p.slab_M;
-  p.zrows_p = max_split_rows(p, p.NP, p.ntw_p);
-  p.zrows_m = max_split_rows(p, p.NM, p.ntw_m);
-  p.n_S = static_cast<size_t>(p.zrows_p) * p.NP;
-  p.n_A = static_cast<size_t>(p.zrows_m) * p.NM;
-  p.n_S2 = sym ? static_cast<size_t>(p.K) * p.NP : 0;
-  p.n_A2 = sym ? static_cast<size_t>(p.K) * p.NM : 0;
-  size_t b = 0;
-  for (size_t n : {p.n_Bc, p.n_Tp, p.n_Tm, p.n_W, p.pm > 0 ? p.n_W : 0, p.n_S, p.n_A, p.n_S2, p.n_A2})
-    b = round_up(b, 256) + n * esize;
-  p.bytes = round_up(b, 256);
+  size_plan(p, sym);
+  if (fit_bytes > 0 && p.bytes > fit_bytes) {  // bytes grow with the slab width: bisect
+    long lo = 1, hi = p.slab_bp - 1;
+    p.slab_bp = 1;
+    size_plan(p, sym);
+    if (p.bytes > fit_bytes) return false;
+    while (lo < hi) {
+      const long mid = (lo + hi + 1) / 2;
+      p.slab_bp = mid;
+      size_plan(p, sym);
+      if (p.bytes <= fit_bytes) lo = mid; else hi = mid - 1;
+    }
+    p.slab_bp = lo;
+    size_plan(p, sym);
+  }
   return true;
 }
 
@@ -994,10 +1016,13 @@ __global__ __launch_bounds__(256) void factor_asym_partial(const double* __restr
 }
 // Runs a partial kernel (launched by `partial` into ASYM_BLOCKS pairs) and the final
 // reduction; copies the two maxima to host2 and synchronises the stream.
+// scratch: a device buffer of at least ASYM_BYTES (NULL: allocated for the call).
+constexpr size_t ASYM_BYTES = (2 * ASYM_BLOCKS + 2) * sizeof(double);
+static_assert(ASYM_BYTES == ASYM_SCRATCH_BYTES, "the header states the check's buffer size");
 template <class F>
-static int max_pair(F&& partial, double* host2, hipStream_t s) {
-  void* buf = nullptr;
-  RI_TRY(dev_alloc(&buf, (2 * ASYM_BLOCKS + 2) * sizeof(double), s));
+static int max_pair(F&& partial, double* host2, hipStream_t s, void* scratch = nullptr) {
+  void* buf = scratch;
+  if (!buf) RI_TRY(dev_alloc(&buf, ASYM_BYTES, s));
   double* part = static_cast<double*>(buf);
   partial(part);
   pair_asym_final<<<1, 256, 0, s>>>(part, part + 2 * ASYM_BLOCKS);
@@ -1005,11 +1030,12 @@ static int max_pair(F&& partial, double* host2, hipStream_t s) {
   if (rc == RI_OK) rc = check_hip(hipMemcpyAsync(host2, part + 2 * ASYM_BLOCKS, 2 * sizeof(double),
                                                  hipMemcpyDeviceToHost, s), "pair_asym copy");
   if (rc == RI_OK) rc = check_hip(hipStreamSynchronize(s), "pair_asym sync");
-  dev_free(buf, s);
+  if (!scratch) dev_free(buf, s);
   return rc;
 }
-int pair_asymmetry(const double* tau, int o, int v, double* host2, hipStream_t s) {
-  return max_pair([&](double* part) { pair_asym_partial<<<ASYM_BLOCKS, 256, 0, s>>>(tau, o, v, part); }, host2, s);
+int pair_asymmetry(const double* tau, int o, int v, double* host2, hipStream_t s, void* scratch = nullptr) {
+  return max_pair([&](double* part) { pair_asym_partial<<<ASYM_BLOCKS, 256, 0, s>>>(tau, o, v, part); }, host2, s,
+                  scratch);
 }
 int factor_asymmetry(const double* B, int naux, int v, double* host2, hipStream_t s) {
   return max_pair([&](double* part) { factor_asym_partial<<<ASYM_BLOCKS, 256, 0, s>>>(B, naux, v, part); }, host2,
@@ -1017,16 +1043,68 @@ int factor_asymmetry(const double* B, int naux, int v, double* host2, hipStream_
 }
 // RI_PPL_CHECK_TAU set (and not "0"): the ladder first checks that tau is
 // pair-symmetric to 1e-12 of its largest element and rejects it otherwise.
-int check_tau_if_asked(const double* tau, int o, int v, hipStream_t s) {
+int check_tau_if_asked(const double* tau, int o, int v, hipStream_t s, void* scratch) {
   const char* e = getenv("RI_PPL_CHECK_TAU");
   if (!e || !*e || (e[0] == '0' && e[1] == 0)) return RI_OK;
   double r[2];
-  RI_TRY(pair_asymmetry(tau, o, v, r, s));
+  RI_TRY(pair_asymmetry(tau, o, v, r, s, scratch));
   if (!(r[0] <= 1e-12 * r[1])) {
     set_error("ri_ppl: tau is not pair-symmetric: max |tau_ij^cd - tau_ji^dc| = %.3e, max |tau| = %.3e", r[0], r[1]);
     return RI_E_ARG;
   }
   return RI_OK;
+}
+
+// Arguments shared by the ladder entry points: pointers, precision, sizes, aliasing
+// of R with the inputs and 8-byte alignment.
+int check_ladder_args(const double* B_vv, const double* tau, int o, int v, int naux, const double* R,
+                      int precision, const char* who) {
+  if (!B_vv || !tau || !R) {
+    set_error("%s: null pointer argument", who);
+    return RI_E_ARG;
+  }
+  if (precision != RI_PREC_FP64 && precision != RI_PREC_FP32 && precision != RI_PREC_BF16X3) {
+    set_error("%s: unknown precision %d", who, precision);
+    return RI_E_ARG;
+  }
+  Plan p;
+  if (!make_plan(o, v, naux, esize_of(precision), p)) {
+    set_error("%s: invalid sizes o=%d v=%d naux=%d", who, o, v, naux);
+    return RI_E_ARG;
+  }
+  const size_t nB = static_cast<size_t>(naux) * v * v * sizeof(double);
+  const size_t nT = static_cast<size_t>(o) * o * v * v * sizeof(double);
+  if (overlaps(R, nT, B_vv, nB) || overlaps(R, nT, tau, nT)) {
+    set_error("%s: R overlaps an input", who);
+    return RI_E_ALIAS;
+  }
+  if ((reinterpret_cast<uintptr_t>(B_vv) | reinterpret_cast<uintptr_t>(tau) |
+       reinterpret_cast<uintptr_t>(R)) & 7) {
+    set_error("%s: arrays must be 8-byte aligned", who);
+    return RI_E_ARG;
+  }
+  return RI_OK;
+}
+
+size_t min_workspace_bytes(int o, int v, int naux, int precision) {
+  if (precision == RI_PREC_BF16X3) return bf16x3_workspace_bytes_min(o, v, naux);
+  Plan p;
+  if (!make_plan(o, v, naux, esize_of(precision), p)) return 0;
+  p.slab_bp = 1;
+  size_plan(p, false);
+  return p.bytes;
+}
+
+int run_fit(const double* B_vv, const double* tau, int o, int v, int naux, double* R, int precision, void* ws,
+            size_t ws_bytes, hipStream_t s) {
+  const long rs = v, qs = static_cast<long>(v) * v;
+  if (precision == RI_PREC_BF16X3) return bf16x3_run(B_vv, qs, rs, tau, o, v, naux, R, ws, ws_bytes, 0, 1, s, true);
+  Plan p;
+  if (!make_plan(o, v, naux, esize_of(precision), p, false, ws_bytes)) {
+    set_error("ladder: no slab plan for o=%d v=%d naux=%d fits %zu bytes of workspace", o, v, naux, ws_bytes);
+    return RI_E_NOMEM;
+  }
+  return run_typed(p, precision, B_vv, qs, rs, tau, R, ws, 0, 1, s);
 }
 
 }  // namespace ppl
@@ -1074,28 +1152,10 @@ int ri_ppl_shard(const double* B_vv, const double* tau, int o, int v, int naux, 
     set_error("ri_ppl: shard %d of %d is not a valid shard", shard, nshards);
     return RI_E_ARG;
   }
-  if (!B_vv || !tau || !R) {
-    set_error("ri_ppl: null pointer argument");
-    return RI_E_ARG;
-  }
-  if (precision != RI_PREC_FP64 && precision != RI_PREC_FP32 && precision != RI_PREC_BF16X3) {
-    set_error("ri_ppl: unknown precision %d", precision);
-    return RI_E_ARG;
-  }
+  RI_TRY(ppl::check_ladder_args(B_vv, tau, o, v, naux, R, precision, "ri_ppl"));
   ppl::Plan p;
   if (!ppl::make_plan(o, v, naux, ppl::esize_of(precision), p)) {
     set_error("ri_ppl: invalid sizes o=%d v=%d naux=%d", o, v, naux);
-    return RI_E_ARG;
-  }
-  const size_t nB = static_cast<size_t>(naux) * v * v * sizeof(double);
-  const size_t nT = static_cast<size_t>(o) * o * v * v * sizeof(double);
-  if (overlaps(R, nT, B_vv, nB) || overlaps(R, nT, tau, nT)) {
-    set_error("ri_ppl: R overlaps an input");
-    return RI_E_ALIAS;
-  }
-  if ((reinterpret_cast<uintptr_t>(B_vv) | reinterpret_cast<uintptr_t>(tau) |
-       reinterpret_cast<uintptr_t>(R)) & 7) {
-    set_error("ri_ppl: arrays must be 8-byte aligned");
     return RI_E_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);

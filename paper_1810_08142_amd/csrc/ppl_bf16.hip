@@ -536,7 +536,29 @@ static long max_split_rows(const MPlan& p, int ncol, int ntw) {
   return best;
 }
 
-static bool make_mplan(int o, int v, int naux, MPlan& p) {
+// Element counts and total bytes of plan p for its slab width p.slab_bp.
+static void size_mplan(MPlan& p) {
+  p.slab_M = p.slab_bp * 256;
+  p.n_B = static_cast<size_t>(p.vp) * p.vp * p.Qp;
+  p.n_Tp = static_cast<size_t>(p.NP) * p.K;
+  p.n_Tm = static_cast<size_t>(p.NM) * p.K;
+  p.n_W = static_cast<size_t>(p.slab_M) * p.K;
+  p.zrows_p = max_split_rows(p, p.NP, p.ntw_p);
+  p.zrows_m = max_split_rows(p, p.NM, p.ntw_m);
+  p.n_S = static_cast<size_t>(p.zrows_p) * p.NP;
+  p.n_A = static_cast<size_t>(p.zrows_m) * p.NM;
+  size_t b = 0;
+  // 16-bit: Bh, Bl, Tph, Tpl, Tmh, Tml, Wph, Wpl, Wmh, Wml; 32-bit: S, A
+  for (size_t n : {p.n_B, p.n_B, p.n_Tp, p.n_Tp, p.n_Tm, p.n_Tm, p.n_W, p.n_W, p.pm > 0 ? p.n_W : 0,
+                   p.pm > 0 ? p.n_W : 0})
+    b = round_up(b, 256) + n * 2;
+  for (size_t n : {p.n_S, p.n_A}) b = round_up(b, 256) + n * 4;
+  p.bytes = round_up(b, 256);
+}
+
+// fit_bytes > 0: the widest slab whose whole workspace fits in fit_bytes (false if not
+// even a one-block-pair slab fits), instead of the W budget RI_PPL_W_BYTES.
+static bool make_mplan(int o, int v, int naux, MPlan& p, size_t fit_bytes = 0) {
   if (o <= 0 || v <= 0 || naux <= 0 || o > 4096 || v > 65536 || naux > (1 << 24)) return false;
   p.o = o;
   p.v = v;
@@ -558,24 +580,24 @@ static bool make_mplan(int o, int v, int naux, MPlan& p) {
   const long budget = env_long("RI_PPL_W_BYTES", 16L << 30);
   long bp = budget / (static_cast<long>(nw) * p.K * 256 * 4);
   bp = std::max(1L, std::min(bp, std::min(p.nbp, 65535L)));
+  if (fit_bytes > 0) bp = std::min(p.nbp, 65535L);
   const long cap = env_long("RI_PPL_SLAB_PAIRS", bp);
   p.slab_bp = std::min(cap, bp);
-  p.slab_M = p.slab_bp * 256;
-  p.n_B = static_cast<size_t>(p.vp) * p.vp * p.Qp;
-  p.n_Tp = static_cast<size_t>(p.NP) * p.K;
-  p.n_Tm = static_cast<size_t>(p.NM) * p.K;
-  p.n_W = static_cast<size_t>(p.slab_M) * p.K;
-  p.zrows_p = max_split_rows(p, p.NP, p.ntw_p);
-  p.zrows_m = max_split_rows(p, p.NM, p.ntw_m);
-  p.n_S = static_cast<size_t>(p.zrows_p) * p.NP;
-  p.n_A = static_cast<size_t>(p.zrows_m) * p.NM;
-  size_t b = 0;
-  // 16-bit: Bh, Bl, Tph, Tpl, Tmh, Tml, Wph, Wpl, Wmh, Wml; 32-bit: S, A
-  for (size_t n : {p.n_B, p.n_B, p.n_Tp, p.n_Tp, p.n_Tm, p.n_Tm, p.n_W, p.n_W, p.pm > 0 ? p.n_W : 0,
-                   p.pm > 0 ? p.n_W : 0})
-    b = round_up(b, 256) + n * 2;
-  for (size_t n : {p.n_S, p.n_A}) b = round_up(b, 256) + n * 4;
-  p.bytes = round_up(b, 256);
+  size_mplan(p);
+  if (fit_bytes > 0 && p.bytes > fit_bytes) {  // bytes grow with the slab width: bisect
+    long lo = 1, hi = p.slab_bp - 1;
+    p.slab_bp = 1;
+    size_mplan(p);
+    if (p.bytes > fit_bytes) return false;
+    while (lo < hi) {
+      const long mid = (lo + hi + 1) / 2;
+      p.slab_bp = mid;
+      size_mplan(p);
+      if (p.bytes <= fit_bytes) lo = mid; else hi = mid - 1;
+    }
+    p.slab_bp = lo;
+    size_mplan(p);
+  }
   return true;
 }
 
@@ -607,10 +629,22 @@ size_t bf16x3_workspace_bytes(int o, int v, int naux) {
   return make_mplan(o, v, naux, p) ? p.bytes : 0;
 }
 
-int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R, void* ws,
-               size_t ws_bytes, int shard, int nshards, hipStream_t s) {
+size_t bf16x3_workspace_bytes_min(int o, int v, int naux) {
   MPlan p;
-  if (!make_mplan(o, v, naux, p)) {
+  if (!make_mplan(o, v, naux, p)) return 0;
+  p.slab_bp = 1;
+  size_mplan(p);
+  return p.bytes;
+}
+
+int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R, void* ws,
+               size_t ws_bytes, int shard, int nshards, hipStream_t s, bool fit) {
+  MPlan p;
+  if (!make_mplan(o, v, naux, p, fit ? ws_bytes : 0)) {
+    if (fit && make_mplan(o, v, naux, p)) {
+      set_error("ladder: no slab plan for o=%d v=%d naux=%d fits %zu bytes of workspace", o, v, naux, ws_bytes);
+      return RI_E_NOMEM;
+    }
     set_error("ladder: invalid sizes o=%d v=%d naux=%d", o, v, naux);
     return RI_E_ARG;
   }

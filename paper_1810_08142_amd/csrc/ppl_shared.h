@@ -104,9 +104,26 @@ void launch_unpack_f32(const float* S, const float* A, int NP, int NM, int o, in
                        double* R, int zp, long zsp, int zm, long zsm, hipStream_t s);
 
 // Mixed-precision ladder (split-bf16, three products, FP32 accumulation).
+// fit: choose the widest slab whose workspace fits ws_bytes (ws must be given);
+// otherwise the default slab plan, which ws_bytes must hold.
 size_t bf16x3_workspace_bytes(int o, int v, int naux);
+size_t bf16x3_workspace_bytes_min(int o, int v, int naux);  // one-block-pair slabs
 int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
-               void* ws, size_t ws_bytes, int shard, int nshards, hipStream_t s);
+               void* ws, size_t ws_bytes, int shard, int nshards, hipStream_t s, bool fit = false);
+
+// Ladder argument checks shared by the entry points (status, error text set).
+int check_ladder_args(const double* B_vv, const double* tau, int o, int v, int naux, const double* R,
+                      int precision, const char* who);
+// With RI_PPL_CHECK_TAU set: reject tau that is not pair-symmetric (synchronises s).
+// scratch: a device buffer of at least ASYM_SCRATCH_BYTES, or NULL to allocate one.
+constexpr size_t ASYM_SCRATCH_BYTES = (2 * 1024 + 2) * sizeof(double);
+int check_tau_if_asked(const double* tau, int o, int v, hipStream_t s, void* scratch = nullptr);
+// Smallest workspace any slab plan needs (one block pair per slab); 0 on invalid sizes.
+size_t min_workspace_bytes(int o, int v, int naux, int precision);
+// The ladder on the caller's workspace ws of ws_bytes, with the widest slab plan that
+// fits in it (RI_E_NOMEM if none does); allocates nothing.
+int run_fit(const double* B_vv, const double* tau, int o, int v, int naux, double* R, int precision, void* ws,
+            size_t ws_bytes, hipStream_t s);
 
 }  // namespace ppl
 }  // namespace ri

@@ -50,6 +50,19 @@ class ProfScope {
   int idx_ = -1;
 };
 
+// While a ProfSuppress lives, ProfScope records nothing on its thread (no HIP events
+// are created), whatever ri_prof_enable says.
+class ProfSuppress {
+ public:
+  ProfSuppress();
+  ~ProfSuppress();
+  ProfSuppress(const ProfSuppress&) = delete;
+  ProfSuppress& operator=(const ProfSuppress&) = delete;
+
+ private:
+  bool prev_;
+};
+
 // Ladder on factors stored with strides: B[q][a][c] at B + q*qs + a*rs + c
 // (R += sum_cd (ac|bd) tau^{cd}_{ij}; workspace allocated on stream s).
 int ppl_strided(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,

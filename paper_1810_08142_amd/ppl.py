@@ -59,6 +59,22 @@ def ppl(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, precision="fp64"
     return R
 
 
+def ppl_noalloc(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, precision="fp64",
+                stream=None) -> torch.Tensor:
+    """The ladder of ``ppl`` with the library's fixed scratch array as its workspace
+    (ri_ppl_noalloc): the call allocates no device memory.  Sizes whose workspace does
+    not fit the array raise with status RI_E_NOMEM."""
+    naux, v = B_vv.shape[0], B_vv.shape[1]
+    o = tau.shape[0]
+    _need(B_vv, "B_vv", (naux, v, v))
+    _need(tau, "tau", (o, o, v, v))
+    _need(R, "R", (o, o, v, v))
+    rc = _lib.lib().ri_ppl_noalloc(B_vv.data_ptr(), tau.data_ptr(), o, v, naux, R.data_ptr(), _prec(precision),
+                                   _stream(stream))
+    _lib.check(rc, "ri_ppl_noalloc")
+    return R
+
+
 def ppl_paper(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, stream=None) -> torch.Tensor:
     """The same sum in the paper's arrangement (full (a, b) build, i <= j pairs only;
     ri_ppl_paper), FP64: the ablation of the tau+- form."""

@@ -99,3 +99,20 @@ def test_exchange_symmetric_form_flops_and_argument_checks(monkeypatch):
         monkeypatch.setenv("RI_PPL_SYM_SLABS", str(slabs))
         got = L.ri_ppl_sym_flops(o, v, n) - contract
         assert build / 2 < got <= build * (1 + 1 / slabs) / 2 * 1.02, (slabs, got / build)
+
+
+def test_allocation_free_ladder_rejects_sizes_beyond_its_scratch():
+    """ri_ppl_noalloc checks its arguments and its fixed scratch size before any device
+    call: bad arguments give RI_E_ARG / RI_E_ALIAS, sizes whose one-block-pair plan needs
+    more than RI_PPL_NOALLOC_MAX_BYTES give RI_E_NOMEM with the sizes in the message."""
+    from paper_1810_08142_amd import _lib
+    L = _lib.lib()
+    assert L.ri_ppl_noalloc(None, None, 2, 3, 4, None, 0, None) == 1
+    assert L.ri_ppl_noalloc(8, 16, 2, 3, 4, 24, 7, None) == 1
+    assert L.ri_ppl_noalloc(4096, 8192, 2, 3, 4, 8192, 0, None) == 2
+    limit = 64 << 20
+    assert f"{limit}".encode() not in L.ri_last_error_msg()
+    for o, v, naux, prec in [(8, 112, 336, 0), (8, 128, 384, 0), (16, 256, 768, 2), (16, 160, 480, 2)]:
+        assert L.ri_ppl_noalloc(8, 1 << 40, o, v, naux, 1 << 44, prec, None) == 3
+        msg = L.ri_last_error_msg()
+        assert f"o={o} v={v} naux={naux}".encode() in msg and f"{limit}".encode() in msg
