@@ -33,7 +33,6 @@
 #include <cmath>
 #include <cstdlib>
 
-#include "gemm.h"
 #include "ppl_shared.h"
 
 namespace ri {
@@ -461,6 +460,122 @@ __global__ __launch_bounds__(256) void contract_f32(const float* __restrict__ W,
   contract_body<float, NTW>(W, Tt, K, M, ncol, C, kz, zs);
 }
 
+// ---------------------------------------------------------------- 3b'. row contraction
+// The second product of the exchange-symmetric form sums along W's rows:
+//   C[r][n] (+)= sum_m W[r][m] T[m][n],   r < rows, m < M, n < ncol
+// W rows have stride ldw, T and C rows stride ncol.  Tile CRM (r) x 16*NTW (n), four
+// waves as in contract_body; W is staged transposed (sA[m][r], padded rows so that
+// the transposing stores spread over the banks), T as there.  `accum` adds into C
+// (the products of later slabs land on the rows of earlier ones in a fixed order).
+// grid (ncol/(16*NTW), rows/CRM), block 256
+template <class T, int NTW>
+__device__ __forceinline__ void contract_rows_body(const T* __restrict__ W, long ldw, const T* __restrict__ Tt,
+                                                   long M, int ncol, T* __restrict__ C, int accum) {
+  typedef Mfma<T> MF;
+  typedef typename MF::vec_t vec_t;
+  constexpr int BN = 16 * NTW;
+  constexpr int RW = CRM / 64;
+  constexpr int VEC = 16 / sizeof(T);          // elements per 16-byte load (along m)
+  constexpr int KV = KC / VEC;                 // loads per W row per chunk
+  constexpr int NA = KC * CRM / (256 * VEC);   // W loads per thread per chunk
+  constexpr int PAD = CRM + 1;
+  __shared__ T sA[2][KC][PAD];
+  __shared__ T sB[2][KC][BN];
+  unsigned tx, ty;
+  xcd_tile(tx, ty);
+  const long n0 = static_cast<long>(tx) * BN, r0 = static_cast<long>(ty) * CRM;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  W += r0 * ldw;
+  Tt += n0;
+  long aoff[NA];
+  int arow[NA], ak[NA];
+#pragma unroll
+  for (int r = 0; r < NA; ++r) {
+    const int id = t + 256 * r;
+    arow[r] = id / KV;
+    ak[r] = (id % KV) * VEC;
+    aoff[r] = arow[r] * ldw + ak[r];
+  }
+  int boff[NTW], blo[NTW];
+#pragma unroll
+  for (int r = 0; r < NTW; ++r) {
+    const int e = t + 256 * r;
+    const int k = e / BN, nn = e % BN;
+    boff[r] = k * ncol + nn;
+    blo[r] = k * BN + nn;
+  }
+  vec_t ra[NA];
+  T rb[NTW];
+  T* sB0 = &sB[0][0][0];
+  auto store_a = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < NA; ++r)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) sA[buf][ak[r] + e][arow[r]] = ra[r][e];
+  };
+  typename MF::acc_t acc[RW][NTW];
+#pragma unroll
+  for (int q = 0; q < RW; ++q)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) acc[q][u] = MF::zero();
+  const int m = lane & 15, kq = lane >> 4;
+  const long nchunks = M / KC;
+#pragma unroll
+  for (int r = 0; r < NA; ++r) ra[r] = *reinterpret_cast<const vec_t*>(W + aoff[r]);
+#pragma unroll
+  for (int r = 0; r < NTW; ++r) rb[r] = Tt[boff[r]];
+  store_a(0);
+#pragma unroll
+  for (int r = 0; r < NTW; ++r) sB0[blo[r]] = rb[r];
+  __syncthreads();
+  for (long ch = 0; ch < nchunks; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nchunks;
+    if (more) {
+      const long ko = (ch + 1) * KC;
+#pragma unroll
+      for (int r = 0; r < NA; ++r) ra[r] = *reinterpret_cast<const vec_t*>(W + aoff[r] + ko);
+#pragma unroll
+      for (int r = 0; r < NTW; ++r) rb[r] = Tt[ko * ncol + boff[r]];
+    }
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int kk = 4 * s + kq;
+      T a[RW];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) a[q] = sA[buf][kk][(w * RW + q) * 16 + m];
+#pragma unroll
+      for (int u = 0; u < NTW; ++u) {
+        const T b = sB[buf][kk][u * 16 + m];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) acc[q][u] = MF::mma(a[q], b, acc[q][u]);
+      }
+    }
+    if (more) {
+      store_a(buf ^ 1);
+#pragma unroll
+      for (int r = 0; r < NTW; ++r) sB0[(buf ^ 1) * KC * BN + blo[r]] = rb[r];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < RW; ++q)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long row = r0 + (w * RW + q) * 16 + MF::drow(r, lane);
+        T* c = C + row * ncol + n0 + u * 16 + m;
+        *c = accum ? *c + acc[q][u][r] : acc[q][u][r];
+      }
+}
+template <int NTW>
+__global__ __launch_bounds__(256) void contract_rows_f64(const double* __restrict__ W, long ldw,
+                                                         const double* __restrict__ Tt, long M, int ncol,
+                                                         double* __restrict__ C, int accum) {
+  contract_rows_body<double, NTW>(W, ldw, Tt, M, ncol, C, accum);
+}
+
 // ---------------------------------------------------------------- 3c. unpack
 // S and A are FP64 (FP64 path) or FP32 (mixed paths); R accumulates in FP64.  S and
 // A may come as zp (zm) partial sums over k, zs (zsm) elements apart, added here in
@@ -557,10 +672,17 @@ struct Plan {
 
 // Splits of the contraction's k range for a launch of `rows` rows and 16*ntw-wide
 // column tiles: enough workgroups to fill the chip about three deep (the kernel's
-// occupancy), at least 32 chunks per split.  kz: summed indices per split.
-static int contract_splits(int ncol, int ntw, long rows, long K, long& kz) {
+// occupancy), and enough that one split's slice of the packed amplitudes (K/z rows of
+// ncol elements) stays within RI_PPL_TAU_CHUNK_MB (default TAU_CHUNK_MB): every row
+// tile streams its split's whole slice, and the workgroups resident together work on
+// the same few splits (z is the slowest grid index), so a slice that fits the last-level
+// cache is fetched from HBM about once instead of once per row tile.  At least 32
+// chunks per split.  kz: summed indices per split.
+static int contract_splits(int ncol, int ntw, long rows, long K, size_t esize, long& kz) {
   const long nwg = (ncol / (16 * ntw)) * (rows / CRM);
   long z = (3 * 256 + nwg - 1) / nwg;
+  const double chunk = static_cast<double>(env_long("RI_PPL_TAU_CHUNK_MB", TAU_CHUNK_MB)) * 1048576.0;
+  z = std::max(z, static_cast<long>(std::ceil(static_cast<double>(K) * ncol * esize / chunk)));
   z = std::max(1L, std::min(z, K / (32 * KC)));
   kz = (K + z - 1) / z;
   kz = (kz + KC - 1) / KC * KC;
@@ -573,7 +695,7 @@ static long max_split_rows(const Plan& p, int ncol, int ntw) {
   long kz;
   const long last = p.nbp - (p.nbp - 1) / p.slab_bp * p.slab_bp;
   long best = 0;
-  for (long rows : {p.slab_M, last * 256}) best = std::max(best, contract_splits(ncol, ntw, rows, p.K, kz) * rows);
+  for (long rows : {p.slab_M, last * 256}) best = std::max(best, contract_splits(ncol, ntw, rows, p.K, p.esize, kz) * rows);
   return best;
 }
 
@@ -778,8 +900,8 @@ static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const d
     int dy0, ndiag;
     diag_pairs(slab0, npairs, dy0, ndiag);
     long kzp = 0, kzm = 0;
-    const int zp = contract_splits(p.NP, p.ntw_p, M, p.K, kzp);
-    const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, p.K, kzm) : 1;
+    const int zp = contract_splits(p.NP, p.ntw_p, M, p.K, p.esize, kzp);
+    const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, p.K, p.esize, kzm) : 1;
     {
       // per valid (a <= b): the v x v matrix (ac|bd) over all c, d, naux products each;
       // off-diagonal and diagonal ab block pairs in two launches
@@ -853,6 +975,27 @@ static void sym_flops(const Plan& p, double& build, double& contract) {
   }
 }
 
+// Column tiles of the row contraction: the widest of 1..4 16-column tiles that divides
+// the padded column count, so that short slabs still launch several workgroups per row
+// tile.  rows: a multiple of CRM; M: a multiple of KC.
+static void launch_contract_rows(const double* W, long ldw, const double* Tt, long M, long rows, int ncol,
+                                 double* C, int accum, hipStream_t s) {
+  const int n16 = ncol / 16;
+  int ntw = 1;
+  for (int c = 4; c >= 1; --c)
+    if (n16 % c == 0) {
+      ntw = c;
+      break;
+    }
+  const dim3 g(n16 / ntw, static_cast<unsigned>(rows / CRM));
+  switch (ntw) {
+    case 4: contract_rows_f64<4><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum); break;
+    case 3: contract_rows_f64<3><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum); break;
+    case 2: contract_rows_f64<2><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum); break;
+    default: contract_rows_f64<1><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum); break;
+  }
+}
+
 static int run_sym(const Plan& p, const double* B_vv, const double* tau, double* R, void* ws, hipStream_t s) {
   typedef K64 KS;
   typedef double T;
@@ -868,8 +1011,6 @@ static int run_sym(const Plan& p, const double* B_vv, const double* tau, double*
   T* A2 = cv.take<T>(p.n_A2);
   const double oo = static_cast<double>(p.o) * p.o;
   RI_TRY(stage_inputs<KS>(p, B_vv, static_cast<long>(p.v) * p.v, p.v, tau, Bc, Tp, Tm, s));
-  GemmArena arena;
-  arena.s = s;
   long first_p1 = -1;  // first row pair of S2 written (by the first slab's second product)
   for (long slab0 = 0; slab0 < p.nbp; slab0 += p.slab_bp) {
     const long npairs = std::min(p.nbp - slab0, p.slab_bp), p1 = slab0 + npairs;
@@ -895,8 +1036,8 @@ static int run_sym(const Plan& p, const double* B_vv, const double* tau, double*
     }
     const size_t w0 = static_cast<size_t>(slab0) * 256 * p.slab_M;  // row slab0*256 of W
     long kzp = 0, kzm = 0;
-    const int zp = contract_splits(p.NP, p.ntw_p, M, K1, kzp);
-    const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, K1, kzm) : 1;
+    const int zp = contract_splits(p.NP, p.ntw_p, M, K1, p.esize, kzp);
+    const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, K1, p.esize, kzm) : 1;
     {
       ProfScope ps(s, KS::contract, 2.0 * (le * ce * p.po + lt * ct * p.pm));
       launch_contract<KS>(p.ntw_p, Wp + w0, Tp + static_cast<size_t>(slab0) * 256 * p.NP, K1, p.slab_M, M, p.NP, S,
@@ -916,16 +1057,20 @@ static int run_sym(const Plan& p, const double* B_vv, const double* tau, double*
     }
     if (p1 < p.nbp) {  // second product: rows cd >= P1 of W against the slab's own T rows
       const long rows = (p.nbp - p1) * 256;
-      const double beta = first_p1 < 0 ? 0.0 : 1.0;
+      const int accum = first_p1 < 0 ? 0 : 1;
       if (first_p1 < 0) first_p1 = p1;
       const size_t wr = static_cast<size_t>(p1) * 256 * p.slab_M;
-      RI_TRY(einsum("km,mn->kn", 1.0, Tensor(Wp + wr, {rows, M}, {p.slab_M, 1}),
-                    Tensor(Tp + static_cast<size_t>(slab0) * 256 * p.NP, {M, p.NP}), beta,
-                    Tensor(S2 + static_cast<size_t>(p1) * 256 * p.NP, {rows, p.NP}), arena, s));
-      if (p.pm > 0)
-        RI_TRY(einsum("km,mn->kn", 1.0, Tensor(Wm + wr, {rows, M}, {p.slab_M, 1}),
-                      Tensor(Tm + static_cast<size_t>(slab0) * 256 * p.NM, {M, p.NM}), beta,
-                      Tensor(A2 + static_cast<size_t>(p1) * 256 * p.NM, {rows, p.NM}), arena, s));
+      double le2, lt2, ld2;
+      count_pairs(p.v, p1, p.nbp - p1, le2, lt2, ld2);
+      ProfScope ps(s, "contract_rows_f64", 2.0 * (le2 * le * p.po + lt2 * lt * p.pm));
+      launch_contract_rows(Wp + wr, p.slab_M, Tp + static_cast<size_t>(slab0) * 256 * p.NP, M, rows, p.NP,
+                           S2 + static_cast<size_t>(p1) * 256 * p.NP, accum, s);
+      RI_TRY(check_launch("contract_rows_f64"));
+      if (p.pm > 0) {
+        launch_contract_rows(Wm + wr, p.slab_M, Tm + static_cast<size_t>(slab0) * 256 * p.NM, M, rows, p.NM,
+                             A2 + static_cast<size_t>(p1) * 256 * p.NM, accum, s);
+        RI_TRY(check_launch("contract_rows_f64"));
+      }
     }
   }
   if (first_p1 >= 0) {

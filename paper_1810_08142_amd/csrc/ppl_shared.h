@@ -12,6 +12,10 @@ namespace ppl {
 
 constexpr int TB = 16;  // virtual block size: a block pair (X <= Y) has 256 slots
 constexpr int NG = 16;  // column granule of the packed amplitudes
+// Largest slice of the packed amplitudes one contraction split reads (MB); see the
+// contraction splits of the ladder paths.  Measured at o=48 v=768 naux=2304: 48-96 MB
+// take the FP64 contraction from 8.0 to 6.5 s; more splits cost unpack time.
+constexpr long TAU_CHUNK_MB = 80;
 
 __host__ __device__ inline void tri_decode(long p, int& x, int& y) {
   // p = y(y+1)/2 + x with 0 <= x <= y
