@@ -151,6 +151,14 @@ double ri_ppl_paper_flops(int o, int v, int naux);
  * ri_ppl_workspace_bytes(o, v, naux, RI_PREC_FP64) plus about v^2 o^2 / 2 doubles of
  * second-product accumulators is taken stream-ordered for the call. */
 int ri_ppl_sym(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream);
+/* The same with a choice of arithmetic (RI_PREC_*), on the slab schedule of the FP64 form.
+ * The reduced precisions keep the error bound of ri_ppl_ex (2e-4 times the ladder of |B_vv|
+ * and |tau|, element by element).  In RI_PREC_BF16X3 the integral tiles are stored with
+ * the (cd) index innermost, so each slab's second product first transposes its block of
+ * them (one read and one write of 8 bytes per element: the hi and lo words of V+ and V-)
+ * and workspace for that transposed block is taken as well. */
+int ri_ppl_sym_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R, int precision,
+                  void* stream);
 /* Algorithmic FLOP of one ri_ppl_sym call (build and both products over its slab
  * schedule, which depends on RI_PPL_W_BYTES, RI_PPL_SLAB_PAIRS and RI_PPL_SYM_SLABS);
  * 0 on invalid arguments. */
@@ -361,6 +369,28 @@ int ri_mlp_train(ri_mlp* net, const float* X, const float* Y, long n, const floa
  * MP2 t2 and the (ia|jb) integrals of sys: t2_ijab, t2_ijba, (ia|jb), (ib|ja),
  * e_i + e_j - e_a - e_b, (e_a - e_b)^2, (e_i - e_j)^2, sqrt((ia|ia)(jb|jb)). */
 int ri_mlp_features(const ri_system* sys, const double* t2_mp2, float* X, void* stream);
+/* Training data of the learned guess, built on the device.
+ * ri_mlp_sample: n amplitude indices drawn with replacement, index k (0 <= k < total)
+ * with probability t2_mp2[k]^2 / sum t2_mp2^2, by the inverse of the cumulative weight:
+ * sample s takes u_s = ((x_s >> 11) + 1/2) 2^-53 of the total weight, x_s the
+ * SplitMix64 output s of `seed` (as in ri_mlp_init), and picks the first index whose
+ * running sum of weights (FP64, index order, in chunks of 4096) exceeds it.  idx: device
+ * int64 [n].  Synchronises stream; RI_E_NUMERIC if the weights sum to zero or a non-finite
+ * value.
+ * ri_mlp_targets: Y[s] = clamp(t2_ccsd[idx[s]] / t2_mp2[idx[s]] - 1, -clip, clip), the
+ * relative correction the network predicts (FP32 out, device arrays).
+ * ri_mlp_fit_scaling: sets the network's feature standardisation to the column means and
+ * standard deviations (FP64 sums in a fixed order, divided by n; a zero deviation becomes
+ * 1) of X [n][d_in] and its output scale to the standard deviation of Y [n] (device
+ * FP32 arrays); synchronises stream.
+ * ri_mlp_standardize: Xn = (X - mean) / std and, when Y and Yn are given, Yn = Y / y_scale
+ * with the network's scaling (d_in <= 8; in place allowed). */
+int ri_mlp_sample(const double* t2_mp2, long total, long n, unsigned long long seed, long* idx, void* stream);
+int ri_mlp_targets(const double* t2_ccsd, const double* t2_mp2, const long* idx, long n, float clip, float* Y,
+                   void* stream);
+int ri_mlp_fit_scaling(ri_mlp* net, const float* X, const float* Y, long n, void* stream);
+int ri_mlp_standardize(const ri_mlp* net, const float* X, const float* Y, long n, float* Xn, float* Yn,
+                       void* stream);
 /* Learned guess: t1 = 0, t2 = t2_MP2 * (1 + y_scale * net), pair-symmetrised (FP64
  * outputs).  The network must have 8 inputs. */
 int ri_mlp_guess(ri_mlp* net, const ri_system* sys, double* t1, double* t2, void* stream);

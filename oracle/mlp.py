@@ -4,9 +4,10 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
 this module; the product path never does.
 
 Plain FP64 numpy version of the learned starting guess for the doubles
-amplitudes: per-amplitude MP2 features, a fully connected network with tanh
-hidden layers, its mean-squared-error loss, the hand-derived backward pass and
-the Adam update.  (The paper has no learned component; this implements the
+amplitudes: per-amplitude MP2 features, the training data (amplitudes sampled with
+probability proportional to t2_MP2^2, their clipped relative corrections, the
+standardisation statistics), a fully connected network with tanh hidden layers,
+its mean-squared-error loss, the hand-derived backward pass and the Adam update.  (The paper has no learned component; this implements the
 method the GPU library adds on top of the MP2 guess of Sec. II.A.)
 
 Parameters are a flat FP64 vector in the order W1, b1, W2, b2, ..., W_out, b_out,
@@ -112,3 +113,50 @@ def features(B: np.ndarray, eps: np.ndarray, o: int, t2: np.ndarray) -> np.ndarr
     diag = np.einsum("iaia->ia", K)
     F[..., 7] = np.sqrt(diag[:, None, :, None] * diag[None, :, None, :])
     return F
+
+
+# ---------------------------------------------------------------- training data
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, c: int) -> int:
+    """Output number c (0, 1, ...) of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014)
+    seeded with `seed`: the state advanced c + 1 times by the golden-ratio increment,
+    then mixed."""
+    z = (seed + (c + 1) * 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def sample_uniforms(n: int, seed: int) -> np.ndarray:
+    """u_s = ((x_s >> 11) + 1/2) 2^-53 in (0, 1), x_s = SplitMix64 output s of seed."""
+    return np.array([((splitmix64(seed, k) >> 11) + 0.5) * 2.0**-53 for k in range(n)])
+
+
+def sample_indices(t2_mp2: np.ndarray, n: int, seed: int):
+    """n indices drawn with probability t2_mp2[k]^2 / sum t2_mp2^2 by the inverse of the
+    cumulative weight: sample s picks the first k whose running sum of weights exceeds
+    u_s times the total.  Returns (indices, running sums, thresholds)."""
+    w = np.asarray(t2_mp2, dtype=np.float64).ravel() ** 2
+    cum = np.cumsum(w)
+    u = sample_uniforms(n, seed) * cum[-1]
+    return np.searchsorted(cum, u, side="right"), cum, u
+
+
+def targets(t2_ccsd: np.ndarray, t2_mp2: np.ndarray, idx, clip: float = 3.0) -> np.ndarray:
+    """Relative corrections t2_CCSD / t2_MP2 - 1 at the flat indices, clipped to [-clip, clip]."""
+    a, b = np.asarray(t2_ccsd).ravel()[idx], np.asarray(t2_mp2).ravel()[idx]
+    return np.clip(a / b - 1.0, -clip, clip)
+
+
+def scaling(X: np.ndarray, Y: np.ndarray):
+    """(mean, std, y_scale): column means and standard deviations of X (divided by n; a
+    zero deviation becomes 1) and the standard deviation of Y (0 becomes 1)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    mean = X.mean(axis=0)
+    std = np.sqrt(((X - mean) ** 2).mean(axis=0))
+    std[std <= 0] = 1.0
+    ys = float(np.sqrt(((Y - Y.mean()) ** 2).mean()))
+    return mean, std, (ys if ys > 0 else 1.0)

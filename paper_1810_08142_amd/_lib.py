@@ -62,6 +62,7 @@ _SIGS = [
     ("ri_ppl_paper", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _dp]),
     ("ri_ppl_paper_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_sym", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _dp]),
+    ("ri_ppl_sym_ex", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _c.c_int, _dp]),
     ("ri_ppl_noalloc", _c.c_int, [_dp, _dp, _c.c_int, _c.c_int, _c.c_int, _dp, _c.c_int, _dp]),
     ("ri_ppl_sym_flops", _c.c_double, [_c.c_int, _c.c_int, _c.c_int]),
     ("ri_ppl_workspace_bytes", _c.c_size_t, [_c.c_int, _c.c_int, _c.c_int, _c.c_int]),
@@ -94,6 +95,10 @@ _SIGS = [
                                 _fltp, _fltp, _dp]),
     ("ri_mlp_features", _c.c_int, [_sysp, _dp, _dp, _dp]),
     ("ri_mlp_guess", _c.c_int, [_c.c_void_p, _sysp, _dp, _dp, _dp]),
+    ("ri_mlp_sample", _c.c_int, [_dp, _c.c_long, _c.c_long, _c.c_ulonglong, _dp, _dp]),
+    ("ri_mlp_targets", _c.c_int, [_dp, _dp, _dp, _c.c_long, _c.c_float, _dp, _dp]),
+    ("ri_mlp_fit_scaling", _c.c_int, [_c.c_void_p, _dp, _dp, _c.c_long, _dp]),
+    ("ri_mlp_standardize", _c.c_int, [_c.c_void_p, _dp, _dp, _c.c_long, _dp, _dp, _dp]),
     ("ri_mlp_save", _c.c_int, [_c.c_void_p, _c.c_char_p]),
     ("ri_mlp_load", _c.c_void_p, [_c.c_char_p]),
 ]

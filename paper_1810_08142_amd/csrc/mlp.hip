@@ -537,6 +537,109 @@ int check_net(const ri_mlp* net, const char* where) {
   return RI_OK;
 }
 
+// ---------------------------------------------------------------- training data
+// Importance sampling of amplitudes with probability proportional to t2_MP2^2, by the
+// inverse of the cumulative weight: sample s takes u_s = ((x_s >> 11) + 1/2) 2^-53 of
+// the total weight, x_s the SplitMix64 output s of `seed`, and picks the first index k
+// whose running sum of weights exceeds it.  The running sums are formed per chunk of
+// SCH elements (in index order) and over the chunks, in FP64.
+constexpr long SCH = 4096;
+__global__ __launch_bounds__(256) void weight_chunks(const double* __restrict__ t, long n, double* csum) {
+  __shared__ double sh[256];
+  const long lo = static_cast<long>(blockIdx.x) * SCH, hi = std::min(n, lo + SCH);
+  double acc = 0.0;
+  for (long k = lo + threadIdx.x; k < hi; k += 256) acc += t[k] * t[k];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) csum[blockIdx.x] = sh[0];
+}
+// cum[c] = sum of the weights of chunks 0 .. c (one thread, chunk order)
+__global__ void chunk_prefix(double* csum, long nch) {
+  if (threadIdx.x || blockIdx.x) return;
+  double acc = 0.0;
+  for (long c = 0; c < nch; ++c) {
+    acc += csum[c];
+    csum[c] = acc;
+  }
+}
+__global__ void sample_kernel(const double* __restrict__ t, long n, const double* __restrict__ cum, long nch,
+                              unsigned long long seed, long ns, long* idx) {
+  const long sidx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (sidx >= ns) return;
+  const double total = cum[nch - 1];
+  const double u = (static_cast<double>(splitmix64(seed, sidx) >> 11) + 0.5) * (1.0 / 9007199254740992.0) * total;
+  long lo = 0, hi = nch - 1;  // first chunk whose cumulative weight exceeds u
+  while (lo < hi) {
+    const long mid = (lo + hi) / 2;
+    if (cum[mid] > u) hi = mid; else lo = mid + 1;
+  }
+  double acc = lo > 0 ? cum[lo - 1] : 0.0;
+  const long k0 = lo * SCH, k1 = std::min(n, k0 + SCH);
+  long pick = k1 - 1;
+  for (long k = k0; k < k1; ++k) {
+    acc += t[k] * t[k];
+    if (acc > u) {
+      pick = k;
+      break;
+    }
+  }
+  idx[sidx] = pick;
+}
+
+// Y[s] = clamp(t2c[idx[s]] / t2m[idx[s]] - 1, -clip, clip)
+__global__ void targets_kernel(const double* __restrict__ t2c, const double* __restrict__ t2m,
+                               const long* __restrict__ idx, long n, float clip, float* Y) {
+  const long sidx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (sidx >= n) return;
+  const long k = idx[sidx];
+  const double r = t2c[k] / t2m[k] - 1.0;
+  Y[sidx] = static_cast<float>(fmin(fmax(r, -static_cast<double>(clip)), static_cast<double>(clip)));
+}
+
+// Column sums (FP64) of the d columns of X [n][d] and of Y [n], optionally about given
+// means (squares of the deviations): part[b][c] for row chunk b, c < d + 1 (column d is Y).
+// grid (nb), block 256: thread c < d + 1 of chunk b sums its column over the chunk.
+constexpr int SROWS = 8192;
+__global__ __launch_bounds__(256) void colstats_partial(const float* __restrict__ X, const float* __restrict__ Y,
+                                                        long n, int d, const double* __restrict__ mean,
+                                                        double* part) {
+  const int c = threadIdx.x;
+  if (c > d) return;
+  const long lo = static_cast<long>(blockIdx.x) * SROWS, hi = std::min(n, lo + SROWS);
+  const double m = mean ? mean[c] : 0.0;
+  double acc = 0.0;
+  for (long r = lo; r < hi; ++r) {
+    const double x = (c < d ? static_cast<double>(X[r * d + c]) : static_cast<double>(Y[r])) - m;
+    acc += mean ? x * x : x;
+  }
+  part[static_cast<long>(blockIdx.x) * (d + 1) + c] = acc;
+}
+// out[c] = sum over chunks of part[b][c] / n, chunk order
+__global__ void colstats_final(const double* __restrict__ part, long nb, int d, long n, double* out) {
+  const int c = threadIdx.x;
+  if (c > d) return;
+  double acc = 0.0;
+  for (long b = 0; b < nb; ++b) acc += part[b * (d + 1) + c];
+  out[c] = acc / static_cast<double>(n);
+}
+
+// Xn = (X - mean) * inv_std, Yn = Y * inv_y (in place allowed)
+__global__ void standardize_kernel(const float* X, const float* Y, long n, int d, Norm nm, float inv_y, float* Xn,
+                                   float* Yn) {
+  const long t = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * (d + 1)) return;
+  const long r = t / (d + 1);
+  const int c = static_cast<int>(t - r * (d + 1));
+  if (c < d)
+    Xn[r * d + c] = (X[r * d + c] - nm.mean[c]) * nm.inv_std[c];
+  else if (Y && Yn)
+    Yn[r] = Y[r] * inv_y;
+}
+
 }  // namespace mlp
 }  // namespace ri
 
@@ -861,6 +964,120 @@ int ri_mlp_features(const ri_system* sys, const double* t2_mp2, float* X, void* 
   }
   dev_free(buf, s);
   return rc;
+}
+
+int ri_mlp_sample(const double* t2_mp2, long total, long n, unsigned long long seed, long* idx, void* stream) {
+  clear_error();
+  if (!t2_mp2 || !idx || total <= 0 || n <= 0 || n > (1L << 30)) {
+    set_error("ri_mlp_sample: invalid argument");
+    return RI_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long nch = (total + mlp::SCH - 1) / mlp::SCH;
+  void* buf = nullptr;
+  RI_TRY(dev_alloc(&buf, static_cast<size_t>(nch) * sizeof(double), s));
+  double* cum = static_cast<double*>(buf);
+  double total_w = 0.0;
+  int rc = RI_OK;
+  do {
+    mlp::weight_chunks<<<static_cast<unsigned>(nch), 256, 0, s>>>(t2_mp2, total, cum);
+    if ((rc = check_launch("weight_chunks"))) break;
+    mlp::chunk_prefix<<<1, 64, 0, s>>>(cum, nch);
+    if ((rc = check_launch("chunk_prefix"))) break;
+    if ((rc = check_hip(hipMemcpyAsync(&total_w, cum + nch - 1, sizeof(double), hipMemcpyDeviceToHost, s),
+                        "ri_mlp_sample copy")))
+      break;
+    if ((rc = check_hip(hipStreamSynchronize(s), "ri_mlp_sample sync"))) break;
+    if (!(total_w > 0.0) || !std::isfinite(total_w)) {
+      set_error("ri_mlp_sample: the weights sum to %g", total_w);
+      rc = RI_E_NUMERIC;
+      break;
+    }
+    mlp::sample_kernel<<<mlp::nblk(n), 256, 0, s>>>(t2_mp2, total, cum, nch, seed, n, idx);
+    rc = check_launch("sample_kernel");
+  } while (false);
+  dev_free(buf, s);
+  return rc;
+}
+
+int ri_mlp_targets(const double* t2_ccsd, const double* t2_mp2, const long* idx, long n, float clip, float* Y,
+                   void* stream) {
+  clear_error();
+  if (!t2_ccsd || !t2_mp2 || !idx || !Y || n <= 0 || !(clip > 0.f)) {
+    set_error("ri_mlp_targets: invalid argument");
+    return RI_E_ARG;
+  }
+  mlp::targets_kernel<<<mlp::nblk(n), 256, 0, static_cast<hipStream_t>(stream)>>>(t2_ccsd, t2_mp2, idx, n, clip,
+                                                                                 Y);
+  return check_launch("targets_kernel");
+}
+
+int ri_mlp_fit_scaling(ri_mlp* net, const float* X, const float* Y, long n, void* stream) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_fit_scaling"));
+  if (!X || !Y || n <= 0 || net->d_in + 1 > 256) {
+    set_error("ri_mlp_fit_scaling: invalid argument");
+    return RI_E_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int d = net->d_in;
+  const long nb = (n + mlp::SROWS - 1) / mlp::SROWS;
+  void* buf = nullptr;
+  RI_TRY(dev_alloc(&buf, (static_cast<size_t>(nb) * (d + 1) + 2 * (d + 1)) * sizeof(double), s));
+  double* part = static_cast<double*>(buf);
+  double* mean = part + nb * (d + 1);
+  double* var = mean + (d + 1);
+  std::vector<double> hm(d + 1), hv(d + 1);
+  int rc = RI_OK;
+  do {
+    mlp::colstats_partial<<<static_cast<unsigned>(nb), 256, 0, s>>>(X, Y, n, d, nullptr, part);
+    mlp::colstats_final<<<1, 256, 0, s>>>(part, nb, d, n, mean);
+    mlp::colstats_partial<<<static_cast<unsigned>(nb), 256, 0, s>>>(X, Y, n, d, mean, part);
+    mlp::colstats_final<<<1, 256, 0, s>>>(part, nb, d, n, var);
+    if ((rc = check_launch("colstats"))) break;
+    if ((rc = check_hip(hipMemcpyAsync(hm.data(), mean, (d + 1) * sizeof(double), hipMemcpyDeviceToHost, s),
+                        "ri_mlp_fit_scaling copy")))
+      break;
+    if ((rc = check_hip(hipMemcpyAsync(hv.data(), var, (d + 1) * sizeof(double), hipMemcpyDeviceToHost, s),
+                        "ri_mlp_fit_scaling copy")))
+      break;
+    rc = check_hip(hipStreamSynchronize(s), "ri_mlp_fit_scaling sync");
+  } while (false);
+  dev_free(buf, s);
+  RI_TRY(rc);
+  for (int c = 0; c <= d; ++c)
+    if (!std::isfinite(hm[c]) || !std::isfinite(hv[c])) {
+      set_error("ri_mlp_fit_scaling: non-finite statistics in column %d", c);
+      return RI_E_NUMERIC;
+    }
+  for (int c = 0; c < d; ++c) {
+    const float sd = static_cast<float>(std::sqrt(hv[c]));
+    net->mean[c] = static_cast<float>(hm[c]);
+    net->stdv[c] = sd > 0.f ? sd : 1.f;
+  }
+  const float ys = static_cast<float>(std::sqrt(hv[d]));
+  net->y_scale = ys > 0.f ? ys : 1.f;
+  return RI_OK;
+}
+
+int ri_mlp_standardize(const ri_mlp* net, const float* X, const float* Y, long n, float* Xn, float* Yn,
+                       void* stream) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_standardize"));
+  if (!X || !Xn || n <= 0 || (Y == nullptr) != (Yn == nullptr) || net->d_in > mlp::NF) {
+    set_error("ri_mlp_standardize: invalid argument");
+    return RI_E_ARG;
+  }
+  mlp::Norm nm{};
+  for (int c = 0; c < net->d_in; ++c) {
+    nm.mean[c] = net->mean[c];
+    nm.inv_std[c] = 1.f / net->stdv[c];
+  }
+  nm.on = 1;
+  const long total = n * (net->d_in + 1);
+  mlp::standardize_kernel<<<mlp::nblk(total), 256, 0, static_cast<hipStream_t>(stream)>>>(
+      X, Y, n, net->d_in, nm, 1.f / net->y_scale, Xn, Yn);
+  return check_launch("standardize_kernel");
 }
 
 int ri_mlp_guess(ri_mlp* net, const ri_system* sys, double* t1, double* t2, void* stream) {

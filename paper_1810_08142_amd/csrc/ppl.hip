@@ -575,15 +575,23 @@ __global__ __launch_bounds__(256) void contract_rows_f64(const double* __restric
                                                          double* __restrict__ C, int accum) {
   contract_rows_body<double, NTW>(W, ldw, Tt, M, ncol, C, accum);
 }
+template <int NTW>
+__global__ __launch_bounds__(256) void contract_rows_f32(const float* __restrict__ W, long ldw,
+                                                         const float* __restrict__ Tt, long M, int ncol,
+                                                         float* __restrict__ C, int accum) {
+  contract_rows_body<float, NTW>(W, ldw, Tt, M, ncol, C, accum);
+}
 
 // ---------------------------------------------------------------- 3c. unpack
 // S and A are FP64 (FP64 path) or FP32 (mixed paths); R accumulates in FP64.  S and
 // A may come as zp (zm) partial sums over k, zs (zsm) elements apart, added here in
-// order.  grid (slab_pairs, ceil(po/16)), block 256
+// order.  perm: the rows of a block pair are in the split path's slot order.
+// grid (slab_pairs, ceil(po/16)), block 256
 template <class T>
 __global__ __launch_bounds__(256) void unpack_kernel(const T* __restrict__ S, const T* __restrict__ A,
                                                      int NP, int NM, int o, int v, long slab0,
-                                                     double* __restrict__ R, int zp, long zsp, int zm, long zsm) {
+                                                     double* __restrict__ R, int zp, long zsp, int zm, long zsm,
+                                                     int perm) {
   __shared__ double sS[256][NG + 1];
   __shared__ double sA[256][NG + 1];
   int Ab, Bb;
@@ -594,14 +602,18 @@ __global__ __launch_bounds__(256) void unpack_kernel(const T* __restrict__ S, co
   const size_t row0 = static_cast<size_t>(blockIdx.x) * 256;
   for (int r = 0; r < 16; ++r) {
     const int slot = r * 16 + (t >> 4), cc = t & 15, lam = lam0 + cc;
+    const int srow = perm ? split_slot(r, t >> 4) : slot;
     double s = 0.0, x = 0.0;
     if (lam < po) {
       int i, j;
       tri_decode(lam, i, j);
-      const size_t is = (row0 + slot) * NP + lam;
+      const size_t is = (row0 + srow) * NP + lam;
       for (int z = 0; z < zp; ++z) s += static_cast<double>(S[z * zsp + is]);
-      if (i < j) {
-        const size_t ia = (row0 + slot) * NM + j * (j - 1) / 2 + i;
+      // the antisymmetric part vanishes at a == b (V-^{aa}_{cd} = (ac|ad) - (ad|ac)); rows
+      // that sum it from separately rounded integrals are not read, so R stays exactly
+      // pair-symmetric
+      if (i < j && !(Ab == Bb && r == (t >> 4))) {
+        const size_t ia = (row0 + srow) * NM + j * (j - 1) / 2 + i;
         for (int z = 0; z < zm; ++z) x += static_cast<double>(A[z * zsm + ia]);
       }
     }
@@ -639,9 +651,9 @@ __global__ __launch_bounds__(256) void unpack_kernel(const T* __restrict__ S, co
 }
 
 void launch_unpack_f32(const float* S, const float* A, int NP, int NM, int o, int v, long slab0, long npairs,
-                       double* R, int zp, long zsp, int zm, long zsm, hipStream_t s) {
+                       double* R, int zp, long zsp, int zm, long zsm, hipStream_t s, int perm) {
   unpack_kernel<float><<<dim3(npairs, (o * (o + 1) / 2 + NG - 1) / NG), 256, 0, s>>>(S, A, NP, NM, o, v, slab0, R,
-                                                                                  zp, zsp, zm, zsm);
+                                                                                  zp, zsp, zm, zsm, perm);
 }
 
 // ---------------------------------------------------------------- tau
@@ -779,6 +791,11 @@ struct K64 {
   static constexpr const char* build_diag = "build_w_f64_diag";
   static constexpr const char* contract = "contract_f64";
   static constexpr const char* unpack = "unpack_f64";
+  static constexpr const char* contract_rows = "contract_rows_f64";
+  template <int NTW>
+  static void rows_k(dim3 g, hipStream_t s, const T* W, long ldw, const T* Tt, long M, int ncol, T* C, int accum) {
+    contract_rows_f64<NTW><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum);
+  }
   static void relayout_k(dim3 g, hipStream_t s, const double* B, long qs, long rs, int v, int naux, int vp, int np,
                          T* Bc) {
     relayout_b_f64<<<g, 256, 0, s>>>(B, qs, rs, v, naux, vp, np, Bc);
@@ -808,6 +825,11 @@ struct K32 {
   static constexpr const char* build_diag = "build_w_f32_diag";
   static constexpr const char* contract = "contract_f32";
   static constexpr const char* unpack = "unpack_f32";
+  static constexpr const char* contract_rows = "contract_rows_f32";
+  template <int NTW>
+  static void rows_k(dim3 g, hipStream_t s, const T* W, long ldw, const T* Tt, long M, int ncol, T* C, int accum) {
+    contract_rows_f32<NTW><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum);
+  }
   static void relayout_k(dim3 g, hipStream_t s, const double* B, long qs, long rs, int v, int naux, int vp, int np,
                          T* Bc) {
     relayout_b_f32<<<g, 256, 0, s>>>(B, qs, rs, v, naux, vp, np, Bc);
@@ -927,7 +949,7 @@ static int run_plan(const Plan& p, const double* B_vv, long qs, long rs, const d
     {
       ProfScope ps(s, KS::unpack, 0.0, 16.0 * oo * (le + lt));
       unpack_kernel<T><<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R, zp,
-                                                                        M * p.NP, zm, M * p.NM);
+                                                                        M * p.NP, zm, M * p.NM, 0);
       RI_TRY(check_launch(KS::unpack));
     }
   }
@@ -978,8 +1000,9 @@ static void sym_flops(const Plan& p, double& build, double& contract) {
 // Column tiles of the row contraction: the widest of 1..4 16-column tiles that divides
 // the padded column count, so that short slabs still launch several workgroups per row
 // tile.  rows: a multiple of CRM; M: a multiple of KC.
-static void launch_contract_rows(const double* W, long ldw, const double* Tt, long M, long rows, int ncol,
-                                 double* C, int accum, hipStream_t s) {
+template <class KS>
+static void launch_contract_rows(const typename KS::T* W, long ldw, const typename KS::T* Tt, long M, long rows,
+                                 int ncol, typename KS::T* C, int accum, hipStream_t s) {
   const int n16 = ncol / 16;
   int ntw = 1;
   for (int c = 4; c >= 1; --c)
@@ -989,16 +1012,16 @@ static void launch_contract_rows(const double* W, long ldw, const double* Tt, lo
     }
   const dim3 g(n16 / ntw, static_cast<unsigned>(rows / CRM));
   switch (ntw) {
-    case 4: contract_rows_f64<4><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum); break;
-    case 3: contract_rows_f64<3><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum); break;
-    case 2: contract_rows_f64<2><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum); break;
-    default: contract_rows_f64<1><<<g, 256, 0, s>>>(W, ldw, Tt, M, ncol, C, accum); break;
+    case 4: KS::template rows_k<4>(g, s, W, ldw, Tt, M, ncol, C, accum); break;
+    case 3: KS::template rows_k<3>(g, s, W, ldw, Tt, M, ncol, C, accum); break;
+    case 2: KS::template rows_k<2>(g, s, W, ldw, Tt, M, ncol, C, accum); break;
+    default: KS::template rows_k<1>(g, s, W, ldw, Tt, M, ncol, C, accum); break;
   }
 }
 
+template <class KS>
 static int run_sym(const Plan& p, const double* B_vv, const double* tau, double* R, void* ws, hipStream_t s) {
-  typedef K64 KS;
-  typedef double T;
+  typedef typename KS::T T;
   Carve cv(ws, p.bytes);
   T* Bc = cv.take<T>(p.n_Bc);
   T* Tp = cv.take<T>(p.n_Tp);
@@ -1052,7 +1075,7 @@ static int run_sym(const Plan& p, const double* B_vv, const double* tau, double*
     {
       ProfScope ps(s, KS::unpack, 0.0, 16.0 * oo * (le + lt));
       unpack_kernel<T><<<dim3(npairs, (p.po + NG - 1) / NG), 256, 0, s>>>(S, A, p.NP, p.NM, p.o, p.v, slab0, R, zp,
-                                                                        M * p.NP, zm, M * p.NM);
+                                                                        M * p.NP, zm, M * p.NM, 0);
       RI_TRY(check_launch(KS::unpack));
     }
     if (p1 < p.nbp) {  // second product: rows cd >= P1 of W against the slab's own T rows
@@ -1062,14 +1085,14 @@ static int run_sym(const Plan& p, const double* B_vv, const double* tau, double*
       const size_t wr = static_cast<size_t>(p1) * 256 * p.slab_M;
       double le2, lt2, ld2;
       count_pairs(p.v, p1, p.nbp - p1, le2, lt2, ld2);
-      ProfScope ps(s, "contract_rows_f64", 2.0 * (le2 * le * p.po + lt2 * lt * p.pm));
-      launch_contract_rows(Wp + wr, p.slab_M, Tp + static_cast<size_t>(slab0) * 256 * p.NP, M, rows, p.NP,
-                           S2 + static_cast<size_t>(p1) * 256 * p.NP, accum, s);
-      RI_TRY(check_launch("contract_rows_f64"));
+      ProfScope ps(s, KS::contract_rows, 2.0 * (le2 * le * p.po + lt2 * lt * p.pm));
+      launch_contract_rows<KS>(Wp + wr, p.slab_M, Tp + static_cast<size_t>(slab0) * 256 * p.NP, M, rows, p.NP,
+                               S2 + static_cast<size_t>(p1) * 256 * p.NP, accum, s);
+      RI_TRY(check_launch(KS::contract_rows));
       if (p.pm > 0) {
-        launch_contract_rows(Wm + wr, p.slab_M, Tm + static_cast<size_t>(slab0) * 256 * p.NM, M, rows, p.NM,
-                             A2 + static_cast<size_t>(p1) * 256 * p.NM, accum, s);
-        RI_TRY(check_launch("contract_rows_f64"));
+        launch_contract_rows<KS>(Wm + wr, p.slab_M, Tm + static_cast<size_t>(slab0) * 256 * p.NM, M, rows, p.NM,
+                                 A2 + static_cast<size_t>(p1) * 256 * p.NM, accum, s);
+        RI_TRY(check_launch(KS::contract_rows));
       }
     }
   }
@@ -1080,7 +1103,7 @@ static int run_sym(const Plan& p, const double* B_vv, const double* tau, double*
     ProfScope ps(s, KS::unpack, 0.0, 16.0 * oo * (le + lt));
     unpack_kernel<T><<<dim3(n2, (p.po + NG - 1) / NG), 256, 0, s>>>(
         S2 + static_cast<size_t>(first_p1) * 256 * p.NP, A2 + static_cast<size_t>(first_p1) * 256 * p.NM, p.NP,
-        p.NM, p.o, p.v, first_p1, R, 1, 0, 1, 0);
+        p.NM, p.o, p.v, first_p1, R, 1, 0, 1, 0, 0);
     RI_TRY(check_launch(KS::unpack));
   }
   return RI_OK;
@@ -1327,26 +1350,15 @@ int ri_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double
   return ri_ppl_ex(B_vv, tau, o, v, naux, R, RI_PREC_FP64, nullptr, 0, stream);
 }
 
-int ri_ppl_sym(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream) {
+int ri_ppl_sym_ex(const double* B_vv, const double* tau, int o, int v, int naux, double* R, int precision,
+                  void* stream) {
   clear_error();
-  if (!B_vv || !tau || !R) {
-    set_error("ri_ppl_sym: null pointer argument");
-    return RI_E_ARG;
-  }
-  ppl::Plan p;
-  if (!ppl::make_plan(o, v, naux, 8, p, true)) {
+  RI_TRY(ppl::check_ladder_args(B_vv, tau, o, v, naux, R, precision, "ri_ppl_sym"));
+  // the slab width is the FP64 plan's for every precision, so the schedule (and the
+  // FLOP count of ri_ppl_sym_flops) does not depend on the precision
+  ppl::Plan p64;
+  if (!ppl::make_plan(o, v, naux, 8, p64, true)) {
     set_error("ri_ppl_sym: invalid sizes o=%d v=%d naux=%d", o, v, naux);
-    return RI_E_ARG;
-  }
-  const size_t nB = static_cast<size_t>(naux) * v * v * sizeof(double);
-  const size_t nT = static_cast<size_t>(o) * o * v * v * sizeof(double);
-  if (overlaps(R, nT, B_vv, nB) || overlaps(R, nT, tau, nT)) {
-    set_error("ri_ppl_sym: R overlaps an input");
-    return RI_E_ALIAS;
-  }
-  if ((reinterpret_cast<uintptr_t>(B_vv) | reinterpret_cast<uintptr_t>(tau) |
-       reinterpret_cast<uintptr_t>(R)) & 7) {
-    set_error("ri_ppl_sym: arrays must be 8-byte aligned");
     return RI_E_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1358,11 +1370,23 @@ int ri_ppl_sym(const double* B_vv, const double* tau, int o, int v, int naux, do
               r[0], r[1]);
     return RI_E_ARG;
   }
+  if (precision == RI_PREC_BF16X3) return ppl::bf16x3_run_sym(B_vv, tau, o, v, naux, R, p64.slab_bp, s);
+  ppl::Plan p = p64;
+  if (precision == RI_PREC_FP32) {
+    ppl::make_plan(o, v, naux, 4, p, true);
+    p.slab_bp = p64.slab_bp;
+    ppl::size_plan(p, true);
+  }
   void* buf = nullptr;
   RI_TRY(dev_alloc(&buf, p.bytes, s));
-  const int rc = ppl::run_sym(p, B_vv, tau, R, buf, s);
+  const int rc = precision == RI_PREC_FP32 ? ppl::run_sym<ppl::K32>(p, B_vv, tau, R, buf, s)
+                                           : ppl::run_sym<ppl::K64>(p, B_vv, tau, R, buf, s);
   dev_free(buf, s);
   return rc;
+}
+
+int ri_ppl_sym(const double* B_vv, const double* tau, int o, int v, int naux, double* R, void* stream) {
+  return ri_ppl_sym_ex(B_vv, tau, o, v, naux, R, RI_PREC_FP64, stream);
 }
 
 double ri_ppl_sym_flops(int o, int v, int naux) {

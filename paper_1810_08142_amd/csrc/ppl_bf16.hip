@@ -152,42 +152,32 @@ __global__ __launch_bounds__(256) void pack_tau_bf16_kernel(const double* __rest
 }
 
 // ---------------------------------------------------------------- build
-// One workgroup = ab block pair x one half of a cd block pair: the 8 c of half h of
-// block Cb by all 16 d of block Db.  Eight waves; wave w owns c in 8h + 4(w>>2) + 0..3
-// and d in 4(w&3) + 0..3, so each fragment read from LDS feeds 12 MFMAs, and a Q step
-// stages 24 factor rows (8 c, 16 d) for 128 (c, d) pairs: 0.75 KB per pair and step.
-// LDS: a ring of three 48 KB slots.  A step occupies two slots (factor rows 0-11 in
-// the first, 12-23 in the second); while step s is computed, the first half of step
-// s + 1 is written into the third slot, and its second half into step s's first slot
-// once every wave has read it.  Each slot holds 16-byte runs [x 12][hl 2][e 32][run 4],
-// the run index XOR-swizzled with sw4(e) so that the lanes of one ds_read_b128 hit
-// distinct banks.
-// D: the workgroups of diagonal ab block pairs (Ab == Bb), blockIdx.y counting them
-// from block Ab = diag_y0; otherwise blockIdx.y is the slab's pair and diagonal pairs
-// exit at once.  In a diagonal pair the (ad|bc) tile is the transpose of the (ac|bd)
-// tile: only the latter is built, and the epilogue reads it back through LDS.
-// grid (nbp*2, slab_pairs or diagonal pairs), block 512
+// Diagonal ab block pairs (a and b in one block).  One workgroup = the block pair x one
+// half of a cd block pair: the 8 c of half h of block Cb by all 16 d of block Db.  Eight
+// waves; wave w owns c in 8h + 4(w>>2) + 0..3 and d in 4(w&3) + 0..3.  A Q step stages
+// 24 factor rows (8 c, 16 d).  LDS: a ring of three 48 KB slots.  A step occupies two
+// slots (factor rows 0-11 in the first, 12-23 in the second); while step s is computed,
+// the first half of step s + 1 is written into the third slot, and its second half
+// into step s's first slot once every wave has read it.  Each slot holds 16-byte runs
+// [x 12][hl 2][e 32][run 4], the run index XOR-swizzled with sw4(e) so that the lanes of
+// one ds_read_b128 hit distinct banks.  In a diagonal pair the (ad|bc) tile is the
+// transpose of the (ac|bd) tile: only the latter is built, and the epilogue reads it
+// back through LDS.  blockIdx.y counts the diagonal pairs from block Ab = diag_y0; the
+// launch covers cd block pairs pcd0 .. nbp-1.
+// grid ((nbp - pcd0)*2, diagonal pairs), block 512
 constexpr int SLOT = 12 * 2 * 32 * 4;  // runs per LDS slot (48 KB)
-template <bool D>
-__device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
+__device__ __forceinline__ void build_diag_body(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
                                                   int Qp, int vp, long slab0, long K, int want_minus, int diag_y0,
-                                                  uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
+                                                  long pcd0, uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
                                                   uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
   __shared__ u32x4_t lds[3 * SLOT];
   static_assert(3 * SLOT * 4 >= 8 * 16 * 256, "the ring holds the transposed tiles");
   const int half = blockIdx.x & 1;
-  const long pcd = blockIdx.x >> 1;
+  const long pcd = pcd0 + (blockIdx.x >> 1);
   int Cb, Db, Ab, Bb;
   tri_decode(pcd, Cb, Db);
-  long pab_loc;
-  if constexpr (D) {
-    Ab = Bb = diag_y0 + static_cast<int>(blockIdx.y);
-    pab_loc = static_cast<long>(Ab) * (Ab + 3) / 2 - slab0;
-  } else {
-    pab_loc = blockIdx.y;
-    tri_decode(slab0 + pab_loc, Ab, Bb);
-    if (Ab == Bb) return;  // built by the diagonal launch (uniform over the workgroup)
-  }
+  Ab = Bb = diag_y0 + static_cast<int>(blockIdx.y);
+  const long pab_loc = static_cast<long>(Ab) * (Ab + 3) / 2 - slab0;
   const int c_base = Cb * TB + half * 8;
   const int d_base = Db * TB;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -264,19 +254,6 @@ __device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ B
           for (int i = 0; i < 4; ++i) o1[i][j] = mfma3(ac[i][0], ac[i][1], bdh, bdl, o1[i][j]);
         }
       }
-      if constexpr (!D) {  // (ad|bc): d fragments of the a rows with c fragments of the b rows
-        bf16x8_t bc[4][2];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int hl = 0; hl < 2; ++hl) bc[i][hl] = frag(xc0 + i, hl, 16);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const bf16x8_t adh = frag(xd0 + j, 0, 0), adl = frag(xd0 + j, 1, 0);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) o2[i][j] = mfma3_mirror(adh, adl, bc[i][0], bc[i][1], o2[i][j]);
-        }
-      }
     };
     u32x4_t sa[6], sb[6];  // first and second half of the next step
     gload(sa, 0, 0);
@@ -307,7 +284,7 @@ __device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ B
     }
   }
 
-  if constexpr (D) {
+  {
     // (ad|bc)[a][b] = (ac|bd)[b][a]: each wave stores its sixteen (ac|bd) tiles in its
     // own 16 KB of the ring, element (a, b) at a*16 + (b ^ a), and reads them back
     // transposed (the loop ended with every wave past its last fragment read)
@@ -372,30 +349,244 @@ __device__ __forceinline__ void build_bf16x3_body(const uint16_t* __restrict__ B
     }
   }
 }
+// Off-diagonal ab block pairs, one integral per wave.  The workgroup covers the same
+// tile as above (ab block pair x half h of cd block pair: 8 c by 16 d, the same 24
+// staged factor rows per Q step), but wave w computes only one of the two integrals,
+// g = w >> 2 (0: (ac|bd), 1: (ad|bc)), for 4 c by 8 d: c = 8h + 4(q >> 1) + i,
+// d = 8(q & 1) + j with q = w & 3.  Per Q step a wave then reads 24 fragments for 96
+// MFMAs instead of 32 (both integrals for 4 x 4 pairs), with the same 128 accumulator
+// registers.  After the Q loop the (ad|bc) waves pass their tiles through LDS (the
+// tiles of both integrals share one lane layout, element (a, b) at lane b + 16(a/4)),
+// and the (ac|bd) waves write W+- for their 32 pairs into the slots of the slot order
+// above.  The launch covers cd block pairs pcd0 .. nbp-1; diagonal ab block pairs exit
+// (the diagonal kernel builds them).
+// grid ((nbp - pcd0)*2, slab_pairs), block 512
+// Workgroup order: the tiles (ab pair, cd half) are dealt in groups of ga ab pairs by
+// gc cd halves (consecutive in both, so a group's factor rows and columns span few
+// blocks), groups round-robin to the eight XCDs in dispatch order (workgroup id mod 8),
+// so the workgroups one XCD runs together share most of their factor data in its L2.
+// One-dimensional grid of 8 * ceil(groups / 8) * ga * gc workgroups; false for the
+// padding ones.
+__device__ inline bool group_tile(long ncdh, long npairs, int ga, int gc, long& cdh, long& pab) {
+  const long L = blockIdx.x, x = L & 7, p = L >> 3, G = static_cast<long>(ga) * gc;
+  const long gi = (p / G) * 8 + x, r = p % G;
+  const long ngc = (ncdh + gc - 1) / gc, nga = (npairs + ga - 1) / ga;
+  if (gi >= ngc * nga) return false;
+  pab = (gi / ngc) * ga + r / gc;
+  cdh = (gi % ngc) * gc + r % gc;
+  return pab < npairs && cdh < ncdh;
+}
+
+__device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
+                                                 int Qp, int vp, long slab0, long K, int want_minus, long pcd0,
+                                                 long npairs, int ga, int gc,
+                                                 uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
+                                                 uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
+  __shared__ u32x4_t lds[3 * SLOT];
+  static_assert(3 * SLOT * 16 >= 4 * 32 * 4 * 64 * 4, "the ring holds the exchanged (ad|bc) tiles");
+  const long nbp = static_cast<long>(vp / TB) * (vp / TB + 1) / 2;
+  long cdh, pab_loc;
+  if (!group_tile(2 * (nbp - pcd0), npairs, ga, gc, cdh, pab_loc)) return;
+  const int half = static_cast<int>(cdh & 1);
+  const long pcd = pcd0 + (cdh >> 1);
+  int Cb, Db, Ab, Bb;
+  tri_decode(pcd, Cb, Db);
+  tri_decode(slab0 + pab_loc, Ab, Bb);
+  if (Ab == Bb) return;  // built by the diagonal launch (uniform over the workgroup)
+  const int c_base = Cb * TB + half * 8;
+  const int d_base = Db * TB;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+
+  // staging: as in build_diag_body
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int hl_w = (wave >> 1) & 1, xt = wave >> 2, e_t = (t >> 2) & 31, run_t = t & 3;
+  const int ag = e_t < 16 ? Ab * TB + e_t : Bb * TB + (e_t - 16);
+  const uint16_t* src = hl_w ? Bl : Bh;
+  const size_t xs = static_cast<size_t>(vp) * Qp;
+  const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint16_t*>(src + static_cast<size_t>(c_base + xt) * xs), 0, -1, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint16_t*>(src + static_cast<size_t>(d_base + xt) * xs), 0, -1, 0x00020000);
+  const int voff = (ag * Qp + run_t * 8) * 2;
+  const int xsb2 = static_cast<int>(xs * 4);
+  const int l0 = xt * 256 + (hl_w * 32 + e_t) * 4 + (run_t ^ sw4(e_t));
+  auto gload = [&](u32x4_t* dst, int h2, int step) {
+    const int qb = step * QC * 2;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int r = 6 * h2 + k;
+      dst[k] = __builtin_bit_cast(u32x4_t, r < 4 ? __builtin_amdgcn_raw_buffer_load_b128(rc, voff, r * xsb2 + qb, 0)
+                                                 : __builtin_amdgcn_raw_buffer_load_b128(rd, voff, (r - 4) * xsb2 + qb, 0));
+    }
+  };
+  auto lstore = [&](const u32x4_t* sv, int slot) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) lds[slot * SLOT + l0 + 512 * k] = sv[k];
+  };
+  const int fe = lane & 15, frun = lane >> 4;
+  const int fsw = frun ^ sw4(fe);
+  const int g = w >> 2, q = w & 3;
+  const int xc0 = (q >> 1) * 4, xd0 = 8 + (q & 1) * 8;
+  // (ac|bd) reads the c rows at the a columns (e 0..15) and the d rows at the b columns
+  // (e 16..31); (ad|bc) the c rows at the b columns and the d rows at the a columns
+  const int ec = g ? 16 : 0, ed = g ? 0 : 16;
+
+  f32x4_t o[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int nsteps = Qp / QC;
+  // in a diagonal cd block pair the slots with c > d carry zero amplitudes: with c in
+  // the upper half and d in the lower one every pair of the wave has c > d
+  const bool zero_w = Cb == Db && half == 1 && (q & 1) == 0;
+  {
+    auto compute = [&](int s0, int s1) {
+      auto frag = [&](int x, int hl, int e_off) -> bf16x8_t {
+        const int base = x < 12 ? s0 * SLOT : s1 * SLOT;
+        const int xx = x < 12 ? x : x - 12;
+        const u32x4_t v = lds[base + ((xx * 2 + hl) * 32 + e_off + fe) * 4 + fsw];
+        return __builtin_bit_cast(bf16x8_t, v);
+      };
+      bf16x8_t cf[4][2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl) cf[i][hl] = frag(xc0 + i, hl, ec);
+      if (g == 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const bf16x8_t dh = frag(xd0 + j, 0, ed), dl = frag(xd0 + j, 1, ed);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) o[i][j] = mfma3(cf[i][0], cf[i][1], dh, dl, o[i][j]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const bf16x8_t dh = frag(xd0 + j, 0, ed), dl = frag(xd0 + j, 1, ed);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) o[i][j] = mfma3_mirror(dh, dl, cf[i][0], cf[i][1], o[i][j]);
+        }
+      }
+    };
+    u32x4_t sa[6], sb[6];
+    gload(sa, 0, 0);
+    gload(sb, 1, 0);
+    lstore(sa, 0);
+    lstore(sb, 1);
+    if (nsteps > 1) {
+      gload(sa, 0, 1);
+      gload(sb, 1, 1);
+    }
+    __syncthreads();
+    int s0 = 0;
+    for (int st = 0; st < nsteps; ++st) {
+      const int s1 = s0 == 2 ? 0 : s0 + 1, sf = s1 == 2 ? 0 : s1 + 1;
+      const bool more = st + 1 < nsteps;
+      if (more) {
+        lstore(sa, sf);
+        if (st + 2 < nsteps) gload(sa, 0, st + 2);
+      }
+      if (!zero_w) compute(s0, s1);
+      __syncthreads();
+      if (more) {
+        lstore(sb, s0);
+        if (st + 2 < nsteps) gload(sb, 1, st + 2);
+        __syncthreads();
+      }
+      s0 = sf;
+    }
+  }
+
+  // exchange: the (ad|bc) wave q stores its tiles at [q][i][j][r][lane] (floats), the
+  // (ac|bd) wave q reads them back in the same order (the loop ended with a barrier
+  // after every wave's last fragment read)
+  float* xb = reinterpret_cast<float*>(lds);
+  if (g == 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xb[(((q * 4 + i) * 8 + j) * 4 + r) * 64 + lane] = o[i][j][r];
+  }
+  __syncthreads();
+  if (g == 1) return;
+
+  // epilogue: (c, d) = (8h + 4(q>>1) + i, 8(q&1) + j) sits in slot
+  // h*128 + ow*16 + i*4 + (j & 3) with ow = 4(q>>1) + 2(q&1) + (j>>2) (the slot order of
+  // the pack); a lane holds (a_in = 4(lane>>4) + r, b_in = lane&15) and stores, per ow
+  // and pair of i, one 16-byte run per array
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a_in = 4 * (lane >> 4) + r, b_in = lane & 15;
+    const size_t row = static_cast<size_t>(pab_loc) * 256 + a_in * 16 + b_in;
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      const int ow = 4 * (q >> 1) + 2 * (q & 1) + jb;
+      const size_t slot0 = static_cast<size_t>(pcd) * 256 + half * 128 + ow * 16;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        uint16_t ph[8], pl[8], mh[8], ml[8];
+#pragma unroll
+        for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+          for (int j2 = 0; j2 < 4; ++j2) {
+            const int i = 2 * hh + i2, j = 4 * jb + j2;
+            const float v1 = o[i][j][r], v2 = xb[(((q * 4 + i) * 8 + j) * 4 + r) * 64 + lane];
+            split_f32(v1 + v2, ph[i2 * 4 + j2], pl[i2 * 4 + j2]);
+            split_f32(v1 - v2, mh[i2 * 4 + j2], ml[i2 * 4 + j2]);
+          }
+        u32x4_t h, l;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          h[k] = static_cast<uint32_t>(ph[2 * k]) | (static_cast<uint32_t>(ph[2 * k + 1]) << 16);
+          l[k] = static_cast<uint32_t>(pl[2 * k]) | (static_cast<uint32_t>(pl[2 * k + 1]) << 16);
+        }
+        const size_t at = row * K + slot0 + 8 * hh;
+        *reinterpret_cast<u32x4_t*>(Wph + at) = h;
+        *reinterpret_cast<u32x4_t*>(Wpl + at) = l;
+        if (want_minus) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            h[k] = static_cast<uint32_t>(mh[2 * k]) | (static_cast<uint32_t>(mh[2 * k + 1]) << 16);
+            l[k] = static_cast<uint32_t>(ml[2 * k]) | (static_cast<uint32_t>(ml[2 * k + 1]) << 16);
+          }
+          *reinterpret_cast<u32x4_t*>(Wmh + at) = h;
+          *reinterpret_cast<u32x4_t*>(Wml + at) = l;
+        }
+      }
+    }
+  }
+}
 __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
-                                                      int Qp, int vp, long slab0, long K, int want_minus,
-                                                      uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
-                                                      uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
-  build_bf16x3_body<false>(Bh, Bl, Qp, vp, slab0, K, want_minus, 0, Wph, Wpl, Wmh, Wml);
+                                                      int Qp, int vp, long slab0, long K, int want_minus, long pcd0,
+                                                      long npairs, int ga, int gc, uint16_t* __restrict__ Wph,
+                                                      uint16_t* __restrict__ Wpl, uint16_t* __restrict__ Wmh,
+                                                      uint16_t* __restrict__ Wml) {
+  build_split_body(Bh, Bl, Qp, vp, slab0, K, want_minus, pcd0, npairs, ga, gc, Wph, Wpl, Wmh, Wml);
 }
 __global__ __launch_bounds__(512) void build_w_bf16x3_diag(const uint16_t* __restrict__ Bh,
                                                            const uint16_t* __restrict__ Bl, int Qp, int vp, long slab0,
-                                                           long K, int want_minus, int diag_y0,
+                                                           long K, int want_minus, int diag_y0, long pcd0,
                                                            uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
                                                            uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
-  build_bf16x3_body<true>(Bh, Bl, Qp, vp, slab0, K, want_minus, diag_y0, Wph, Wpl, Wmh, Wml);
+  build_diag_body(Bh, Bl, Qp, vp, slab0, K, want_minus, diag_y0, pcd0, Wph, Wpl, Wmh, Wml);
 }
 
 // ---------------------------------------------------------------- contract
-// C[m][n] = sum_k W[m][k] T[n][k] (both split); tile CBM (m) x 16*NTW (n); CBM/32
-// waves, wave w owns rows 32w..32w+31 (two m tiles) and all columns.  LDS holds 16-byte
-// runs [row][8 runs: hl 2 x run 4], run index XOR-swizzled with sw8(row).  The k range
-// may be split over grid.z: split z sums k in [z*kz, min(K, (z+1)*kz)) into C + z*zs.
+// C[m][n] (+)= sum_k W[m][k] T[n][k] (both split; W rows lda, T rows ldb apart); tile
+// CBM (m) x 16*NTW (n); CBM/32 waves, wave w owns rows 32w..32w+31 (two m tiles) and all
+// columns.  LDS holds 16-byte runs [row][8 runs: hl 2 x run 4], run index XOR-swizzled
+// with sw8(row).  The k range may be split over grid.z: split z sums k in
+// [z*kz, min(K, (z+1)*kz)) into C + z*zs.  accum adds into C instead of writing it.
 // grid (ncol/(16*NTW), rows/CBM, splits), block CNT
 template <int NTW>
 __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
-                                                       const uint16_t* __restrict__ Th, const uint16_t* __restrict__ Tl,
-                                                       long K, int ncol, float* __restrict__ C, long kz, long zs) {
+                                                       long lda, const uint16_t* __restrict__ Th,
+                                                       const uint16_t* __restrict__ Tl, long ldb, long K, int ncol,
+                                                       float* __restrict__ C, long kz, long zs, int accum) {
   constexpr int BN = 16 * NTW;
   constexpr int ARUNS = CBM * 2 * 4, BRUNS = BN * 2 * 4;
   __shared__ u32x4_t sA[2 * ARUNS];
@@ -419,7 +610,7 @@ __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restric
     const int id = t + CNT * r;
     const int row = id >> 3, hl = (id >> 2) & 1, run = id & 3;
     asrc[r] = hl ? Wl : Wh;
-    aoff[r] = static_cast<size_t>(m0 + row) * K + k_lo + run * 8;
+    aoff[r] = static_cast<size_t>(m0 + row) * lda + k_lo + run * 8;
     alo[r] = row * 8 + ((hl * 4 + run) ^ sw8(row));
   }
   size_t boff[BPER];
@@ -430,7 +621,7 @@ __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restric
     const int id = t + CNT * r;
     const int row = (id >> 3) < BN ? (id >> 3) : 0, hl = (id >> 2) & 1, run = id & 3;
     bsrc[r] = hl ? Tl : Th;
-    boff[r] = static_cast<size_t>(n0 + row) * K + k_lo + run * 8;
+    boff[r] = static_cast<size_t>(n0 + row) * ldb + k_lo + run * 8;
     blo[r] = id < BRUNS ? row * 8 + ((hl * 4 + run) ^ sw8(row)) : -1;
   }
   const int fr = lane & 15, frun = lane >> 4;
@@ -499,17 +690,55 @@ __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restric
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const long row = m0 + w * 32 + i * 16 + 4 * (lane >> 4) + r;
-        C[row * ncol + n0 + u * 16 + (lane & 15)] = acc[i][u][r];
+        float* c = C + row * ncol + n0 + u * 16 + (lane & 15);
+        *c = accum ? *c + acc[i][u][r] : acc[i][u][r];
       }
+}
+
+// ---------------------------------------------------------------- slot order
+// Tn[n][256 q + 16 x + y] = T[n][256 q + split_slot(x, y)]: packed tau with the slots of
+// every block pair in natural order (16-bit words; rows of K).  grid (K/256, rows), block 256
+__global__ __launch_bounds__(256) void natural_slots_u16(const uint16_t* __restrict__ T, long K,
+                                                         uint16_t* __restrict__ Tn) {
+  const size_t base = static_cast<size_t>(blockIdx.y) * K + static_cast<size_t>(blockIdx.x) * 256;
+  const int nu = threadIdx.x;
+  Tn[base + nu] = T[base + split_slot(nu >> 4, nu & 15)];
+}
+
+// ---------------------------------------------------------------- transpose
+// dst[c][r] = src[r][c] for r < rows, c < cols (16-bit words; src rows lds apart, dst rows
+// ldd apart), through 64 x 64 LDS tiles.  rows and cols are multiples of 64.
+// grid (cols/64, rows/64), block 256
+__global__ __launch_bounds__(256) void transpose_u16(const uint16_t* __restrict__ src, long lds, uint16_t* __restrict__ dst,
+                                                     long ldd) {
+  __shared__ uint16_t tile[64][66];
+  const long c0 = static_cast<long>(blockIdx.x) * 64, r0 = static_cast<long>(blockIdx.y) * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = ty + 4 * k;
+    tile[r][tx] = src[(r0 + r) * lds + c0 + tx];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int c = ty + 4 * k;
+    dst[(c0 + c) * ldd + r0 + tx] = tile[tx][c];
+  }
 }
 
 // ---------------------------------------------------------------- host
 // Splits of the contraction's k range for a launch of `rows` rows and 16*ntw-wide
 // column tiles: enough workgroups to fill the chip about two deep (the kernel's
-// occupancy), at least 32 steps per split.  kz: summed indices per split.
+// occupancy), and enough that one split's slice of the packed amplitudes (hi and lo
+// words, ncol rows of K/z) stays within RI_PPL_TAU_CHUNK_MB (default TAU_CHUNK_MB), for the
+// reason given with the FP64 path's splits.  At least 32 steps per split.  kz: summed
+// indices per split.
 static int contract_splits(int ncol, int ntw, long rows, long K, long& kz) {
   const long nwg = (ncol / (16 * ntw)) * (rows / CBM);
   long z = (2 * 256 + nwg - 1) / nwg;
+  const double chunk = static_cast<double>(env_long("RI_PPL_TAU_CHUNK_MB", TAU_CHUNK_MB)) * 1048576.0;
+  z = std::max(z, static_cast<long>(std::ceil(static_cast<double>(K) * ncol * 4.0 / chunk)));
   z = std::max(1L, std::min(z, K / (32 * KB)));
   kz = (K + z - 1) / z;
   kz = (kz + KB - 1) / KB * KB;
@@ -601,27 +830,50 @@ static bool make_mplan(int o, int v, int naux, MPlan& p, size_t fit_bytes = 0) {
   return true;
 }
 
-// The k range is split `splits` ways (kz each) into partial outputs rows*ncol apart.
+// The k range (extent K) is split `splits` ways (kz each) into partial outputs rows*ncol
+// apart.
+struct CArgs {
+  const uint16_t *Wh, *Wl;
+  long lda;
+  const uint16_t *Th, *Tl;
+  long ldb, K, rows;
+  int ncol;
+  float* C;
+  int splits;
+  long kz;
+  int accum;
+};
 template <int NTW>
-static void launch_c(const uint16_t* Wh, const uint16_t* Wl, const uint16_t* Th, const uint16_t* Tl, long K,
-                     long rows, int ncol, float* C, int splits, long kz, hipStream_t s) {
-  contract_bf16x3<NTW><<<dim3(ncol / (16 * NTW), rows / CBM, splits), CNT, 0, s>>>(Wh, Wl, Th, Tl, K, ncol, C, kz,
-                                                                                   rows * ncol);
+static void launch_c(const CArgs& a, hipStream_t s) {
+  contract_bf16x3<NTW><<<dim3(a.ncol / (16 * NTW), a.rows / CBM, a.splits), CNT, 0, s>>>(
+      a.Wh, a.Wl, a.lda, a.Th, a.Tl, a.ldb, a.K, a.ncol, a.C, a.kz, a.rows * a.ncol, a.accum);
 }
 
-static void launch_contract(int ntw, const uint16_t* Wh, const uint16_t* Wl, const uint16_t* Th, const uint16_t* Tl,
-                            long K, long rows, int ncol, float* C, int splits, long kz, hipStream_t s) {
+static void launch_contract(int ntw, const CArgs& a, hipStream_t s) {
   switch (ntw) {
-    case 1: launch_c<1>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
-    case 2: launch_c<2>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
-    case 3: launch_c<3>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
-    case 4: launch_c<4>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
-    case 5: launch_c<5>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
-    case 6: launch_c<6>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
-    case 7: launch_c<7>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
-    case 8: launch_c<8>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
-    default: launch_c<9>(Wh, Wl, Th, Tl, K, rows, ncol, C, splits, kz, s); break;
+    case 1: launch_c<1>(a, s); break;
+    case 2: launch_c<2>(a, s); break;
+    case 3: launch_c<3>(a, s); break;
+    case 4: launch_c<4>(a, s); break;
+    case 5: launch_c<5>(a, s); break;
+    case 6: launch_c<6>(a, s); break;
+    case 7: launch_c<7>(a, s); break;
+    case 8: launch_c<8>(a, s); break;
+    default: launch_c<9>(a, s); break;
   }
+}
+
+// Off-diagonal build of the slab's ab block pairs [slab0, slab0 + npairs) against cd
+// block pairs pcd0 .. nbp-1, in the grouped workgroup order (groups of one ab block
+// pair by 32 cd halves: measured best of 1x32, 2x16, 4x8, 8x4 at o=48 v=768 naux=2304).
+constexpr int GROUP_AB = 1, GROUP_CD = 32;
+static void launch_build(const uint16_t* Bh, const uint16_t* Bl, const MPlan& p, long slab0, long npairs, long pcd0,
+                         uint16_t* Wph, uint16_t* Wpl, uint16_t* Wmh, uint16_t* Wml, hipStream_t s) {
+  const long ngroups = ((2 * (p.nbp - pcd0) + GROUP_CD - 1) / GROUP_CD) * ((npairs + GROUP_AB - 1) / GROUP_AB);
+  const long nwg = (ngroups + 7) / 8 * 8 * GROUP_AB * GROUP_CD;
+  build_w_bf16x3<<<dim3(static_cast<unsigned>(nwg)), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K, p.pm > 0 ? 1 : 0,
+                                                                   pcd0, npairs, GROUP_AB, GROUP_CD, Wph, Wpl, Wmh,
+                                                                   Wml);
 }
 
 size_t bf16x3_workspace_bytes(int o, int v, int naux) {
@@ -703,22 +955,21 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
       const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, p.K, kzm) : 1;
       {  // off-diagonal and diagonal ab block pairs in two launches
         ProfScope ps(s, "build_w_bf16x3", 2.0 * naux * vv * (le - ld));
-        build_w_bf16x3<<<dim3(p.nbp * 2, npairs), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K, p.pm > 0 ? 1 : 0,
-                                                              Wph, Wpl, Wmh, Wml);
+        launch_build(Bh, Bl, p, slab0, npairs, 0, Wph, Wpl, Wmh, Wml, s);
         if ((rc = check_launch("build_w_bf16x3"))) break;
       }
       if (ndiag > 0) {
         ProfScope ps(s, "build_w_bf16x3_diag", 2.0 * naux * vv * ld);
         build_w_bf16x3_diag<<<dim3(p.nbp * 2, ndiag), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K,
-                                                                   p.pm > 0 ? 1 : 0, dy0, Wph, Wpl, Wmh, Wml);
+                                                                   p.pm > 0 ? 1 : 0, dy0, 0, Wph, Wpl, Wmh, Wml);
         if ((rc = check_launch("build_w_bf16x3_diag"))) break;
       }
       {
         ProfScope ps(s, "contract_bf16x3", 2.0 * (le * pv * p.po + lt * pvm * p.pm));
-        launch_contract(p.ntw_p, Wph, Wpl, Tph, Tpl, p.K, M, p.NP, S, zp, kzp, s);
+        launch_contract(p.ntw_p, CArgs{Wph, Wpl, p.K, Tph, Tpl, p.K, p.K, M, p.NP, S, zp, kzp, 0}, s);
         if ((rc = check_launch("contract_bf16x3(+)"))) break;
         if (p.pm > 0) {
-          launch_contract(p.ntw_m, Wmh, Wml, Tmh, Tml, p.K, M, p.NM, A, zm, kzm, s);
+          launch_contract(p.ntw_m, CArgs{Wmh, Wml, p.K, Tmh, Tml, p.K, p.K, M, p.NM, A, zm, kzm, 0}, s);
           if ((rc = check_launch("contract_bf16x3(-)"))) break;
         }
       }
@@ -730,6 +981,166 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
     }
   } while (false);
   if (own) dev_free(buf, s);
+  return rc;
+}
+
+// ---------------------------------------------------------------- exchange symmetry
+// The exchange-symmetric ladder (factors symmetric in their virtual indices) in split
+// bf16: as the FP64 form, slab [P0, P1) builds the cd block pairs >= P0 only and uses
+// each built element twice.  W here is [ab slot][cd slot], so for the second product
+//   S2[cd][n] += sum_{ab in slab} W[ab][cd] T[n][ab]        (rows cd >= P1)
+// the block W[:, P1*256:] is first transposed (transpose_u16, 16-bit words) into
+// W2[cd][ab], after which the product is the contraction kernel with the slab's slice of
+// T, accumulating into S2 in slab order.  The ab index of W is in natural slot order and
+// its cd index in the split order (split_slot), so the second product sums against a
+// natural-order copy of T and leaves S2's rows in the split order, which the final
+// unpack reads as such.  S2 and A2 are FP32 and unpacked once at the end.
+// slab_bp: the slab width (block pairs), the same for every precision of this form.
+int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, double* R, long slab_bp,
+                   hipStream_t s) {
+  MPlan p;
+  if (!make_mplan(o, v, naux, p)) {
+    set_error("ri_ppl_sym: invalid sizes o=%d v=%d naux=%d", o, v, naux);
+    return RI_E_ARG;
+  }
+  p.slab_bp = std::max(1L, std::min(slab_bp, p.nbp));
+  size_mplan(p);
+  const size_t n_S2 = static_cast<size_t>(p.K) * p.NP, n_A2 = static_cast<size_t>(p.K) * p.NM;
+  const size_t n_W2 = p.n_W;  // (K - P1*256) x M <= K x slab_M per array
+  const int nw = p.pm > 0 ? 4 : 2;
+  const size_t bytes = p.bytes + round_up(n_S2 * 4, 256) + round_up(n_A2 * 4, 256) + nw * round_up(n_W2 * 2, 256) +
+                       2 * round_up(p.n_Tp * 2, 256) + 2 * round_up(p.n_Tm * 2, 256);
+  void* buf = nullptr;
+  RI_TRY(dev_alloc(&buf, bytes, s));
+  Carve cv(buf, bytes);
+  uint16_t* Bh = cv.take<uint16_t>(p.n_B);
+  uint16_t* Bl = cv.take<uint16_t>(p.n_B);
+  uint16_t* Tph = cv.take<uint16_t>(p.n_Tp);
+  uint16_t* Tpl = cv.take<uint16_t>(p.n_Tp);
+  uint16_t* Tmh = cv.take<uint16_t>(p.n_Tm);
+  uint16_t* Tml = cv.take<uint16_t>(p.n_Tm);
+  uint16_t* Wph = cv.take<uint16_t>(p.n_W);
+  uint16_t* Wpl = cv.take<uint16_t>(p.n_W);
+  uint16_t* Wmh = cv.take<uint16_t>(p.pm > 0 ? p.n_W : 0);
+  uint16_t* Wml = cv.take<uint16_t>(p.pm > 0 ? p.n_W : 0);
+  float* S = cv.take<float>(p.n_S);
+  float* A = cv.take<float>(p.n_A);
+  float* S2 = cv.take<float>(n_S2);
+  float* A2 = cv.take<float>(n_A2);
+  uint16_t* W2[4];
+  for (int k = 0; k < nw; ++k) W2[k] = cv.take<uint16_t>(n_W2);
+  uint16_t* Tnph = cv.take<uint16_t>(p.n_Tp);  // natural slot order
+  uint16_t* Tnpl = cv.take<uint16_t>(p.n_Tp);
+  uint16_t* Tnmh = cv.take<uint16_t>(p.n_Tm);
+  uint16_t* Tnml = cv.take<uint16_t>(p.n_Tm);
+
+  int rc = RI_OK;
+  const double oo = static_cast<double>(o) * o;
+  const double vv = static_cast<double>(v) * v;
+  const long qs = static_cast<long>(v) * v, rs = v;
+  do {
+    {
+      ProfScope ps(s, "split_b_bf16", 0.0, 8.0 * vv * naux + 4.0 * vv * naux);
+      split_b_kernel<<<dim3(p.Qp / 32, p.vp / 32 + (p.vp % 32 ? 1 : 0), p.vp), 256, 0, s>>>(B, qs, rs, v, naux, p.vp,
+                                                                                           p.Qp, Bh, Bl);
+      if ((rc = check_launch("split_b_kernel"))) break;
+    }
+    {
+      ProfScope ps(s, "pack_tau_bf16", 0.0, 0.0);
+      pack_tau_bf16_kernel<<<dim3(p.nbp, p.NP), 256, 0, s>>>(tau, o, v, p.K, +1, Tph, Tpl);
+      if ((rc = check_launch("pack_tau_bf16(+)"))) break;
+      if (p.pm > 0) {
+        pack_tau_bf16_kernel<<<dim3(p.nbp, p.NM), 256, 0, s>>>(tau, o, v, p.K, -1, Tmh, Tml);
+        if ((rc = check_launch("pack_tau_bf16(-)"))) break;
+      }
+      const dim3 gp(static_cast<unsigned>(p.nbp), p.NP), gm(static_cast<unsigned>(p.nbp), p.NM);
+      natural_slots_u16<<<gp, 256, 0, s>>>(Tph, p.K, Tnph);
+      natural_slots_u16<<<gp, 256, 0, s>>>(Tpl, p.K, Tnpl);
+      if (p.pm > 0) {
+        natural_slots_u16<<<gm, 256, 0, s>>>(Tmh, p.K, Tnmh);
+        natural_slots_u16<<<gm, 256, 0, s>>>(Tml, p.K, Tnml);
+      }
+      if ((rc = check_launch("natural_slots_u16"))) break;
+    }
+    long first_p1 = -1;
+    for (long slab0 = 0; slab0 < p.nbp && rc == RI_OK; slab0 += p.slab_bp) {
+      const long npairs = std::min(p.slab_bp, p.nbp - slab0), p1 = slab0 + npairs;
+      const long M = npairs * 256, K1 = p.K - slab0 * 256;
+      double le, lt, ld, ce, ct, cd;
+      count_pairs(v, slab0, npairs, le, lt, ld);
+      count_pairs(v, slab0, p.nbp - slab0, ce, ct, cd);
+      int dy0, ndiag;
+      diag_pairs(slab0, npairs, dy0, ndiag);
+      const double per_ab = 2.0 * naux * (2.0 * ct + (ce - ct));
+      {
+        ProfScope ps(s, "build_w_bf16x3", per_ab * (le - ld));
+        launch_build(Bh, Bl, p, slab0, npairs, slab0, Wph, Wpl, Wmh, Wml, s);
+        if ((rc = check_launch("build_w_bf16x3"))) break;
+      }
+      if (ndiag > 0) {
+        ProfScope ps(s, "build_w_bf16x3_diag", per_ab * ld);
+        build_w_bf16x3_diag<<<dim3((p.nbp - slab0) * 2, ndiag), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K,
+                                                                             p.pm > 0 ? 1 : 0, dy0, slab0, Wph, Wpl,
+                                                                             Wmh, Wml);
+        if ((rc = check_launch("build_w_bf16x3_diag"))) break;
+      }
+      long kzp = 0, kzm = 0;
+      const int zp = contract_splits(p.NP, p.ntw_p, M, K1, kzp);
+      const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, K1, kzm) : 1;
+      const size_t c0 = static_cast<size_t>(slab0) * 256;  // first cd slot built for the slab
+      {
+        ProfScope ps(s, "contract_bf16x3", 2.0 * (le * ce * p.po + lt * ct * p.pm));
+        launch_contract(p.ntw_p, CArgs{Wph + c0, Wpl + c0, p.K, Tph + c0, Tpl + c0, p.K, K1, M, p.NP, S, zp, kzp, 0}, s);
+        if ((rc = check_launch("contract_bf16x3(+)"))) break;
+        if (p.pm > 0) {
+          launch_contract(p.ntw_m, CArgs{Wmh + c0, Wml + c0, p.K, Tmh + c0, Tml + c0, p.K, K1, M, p.NM, A, zm, kzm, 0},
+                          s);
+          if ((rc = check_launch("contract_bf16x3(-)"))) break;
+        }
+      }
+      {
+        ProfScope ps(s, "unpack_f32", 0.0, 16.0 * oo * (le + lt));
+        launch_unpack_f32(S, A, p.NP, p.NM, o, v, slab0, npairs, R, zp, M * p.NP, zm, M * p.NM, s);
+        if ((rc = check_launch("unpack_f32"))) break;
+      }
+      if (p1 < p.nbp) {  // second product over the rows cd >= P1
+        const long rows2 = (p.nbp - p1) * 256;
+        const size_t c1 = static_cast<size_t>(p1) * 256;
+        const int accum = first_p1 < 0 ? 0 : 1;
+        if (first_p1 < 0) first_p1 = p1;
+        {
+          ProfScope ps(s, "transpose_w_bf16", 0.0, 4.0 * nw * static_cast<double>(M) * rows2);
+          uint16_t* Ws[4] = {Wph, Wpl, Wmh, Wml};
+          for (int k = 0; k < nw; ++k)
+            transpose_u16<<<dim3(static_cast<unsigned>(rows2 / 64), static_cast<unsigned>(M / 64)), 256, 0, s>>>(
+                Ws[k] + c1, p.K, W2[k], M);
+          if ((rc = check_launch("transpose_u16"))) break;
+        }
+        double le2, lt2, ld2;
+        count_pairs(v, p1, p.nbp - p1, le2, lt2, ld2);
+        ProfScope ps(s, "contract2_bf16x3", 2.0 * (le2 * le * p.po + lt2 * lt * p.pm));
+        launch_contract(p.ntw_p, CArgs{W2[0], W2[1], M, Tnph + c0, Tnpl + c0, p.K, M, rows2, p.NP,
+                                       S2 + c1 * p.NP, 1, M, accum}, s);
+        if ((rc = check_launch("contract2_bf16x3(+)"))) break;
+        if (p.pm > 0) {
+          launch_contract(p.ntw_m, CArgs{W2[2], W2[3], M, Tnmh + c0, Tnml + c0, p.K, M, rows2, p.NM,
+                                         A2 + c1 * p.NM, 1, M, accum}, s);
+          if ((rc = check_launch("contract2_bf16x3(-)"))) break;
+        }
+      }
+    }
+    if (rc == RI_OK && first_p1 >= 0) {
+      const long n2 = p.nbp - first_p1;
+      double le, lt, ld;
+      count_pairs(v, first_p1, n2, le, lt, ld);
+      ProfScope ps(s, "unpack_f32", 0.0, 16.0 * oo * (le + lt));
+      launch_unpack_f32(S2 + static_cast<size_t>(first_p1) * 256 * p.NP,
+                        A2 + static_cast<size_t>(first_p1) * 256 * p.NM, p.NP, p.NM, o, v, first_p1, n2, R, 1, 0, 1, 0,
+                        s, 1);
+      rc = check_launch("unpack_f32");
+    }
+  } while (false);
+  dev_free(buf, s);
   return rc;
 }
 

@@ -26,6 +26,14 @@ __host__ __device__ inline void tri_decode(long p, int& x, int& y) {
   x = static_cast<int>(p - yy * (yy + 1) / 2);
 }
 
+// The split-bf16 path stores the 256 slots of a cd block pair in the build's wave
+// order: the pair (x_in, y_in) (x_in the first index of the pair, 0..15) sits in slot
+// 128h + 16w + 4i + j with h = x_in >> 3, w = 4 ((x_in >> 2) & 1) + (y_in >> 2),
+// i = x_in & 3, j = y_in & 3 (the natural order is 16 x_in + y_in).
+__host__ __device__ inline int split_slot(int x_in, int y_in) {
+  return 128 * (x_in >> 3) + 16 * (4 * ((x_in >> 2) & 1) + (y_in >> 2)) + 4 * (x_in & 3) + (y_in & 3);
+}
+
 // Contraction column tiling: ntw 16-wide column tiles per workgroup tile (1..maxw),
 // chosen to minimise the padded column count (ties: wider tiles).
 // Columns per contraction tile (ntw tiles of 16) for ncols output columns.  A tile
@@ -104,8 +112,10 @@ inline void diag_pairs(long p0, long n, int& y0, int& count) {
 
 // R += mirrored S +- A from FP32 slab results (shared unpack kernel).
 // S, A: zp (zm) partial sums over k, zsp (zsm) elements apart, added in order.
+// perm: S and A rows are in the split path's slot order (split_slot) instead of the
+// natural one.
 void launch_unpack_f32(const float* S, const float* A, int NP, int NM, int o, int v, long slab0, long npairs,
-                       double* R, int zp, long zsp, int zm, long zsm, hipStream_t s);
+                       double* R, int zp, long zsp, int zm, long zsm, hipStream_t s, int perm = 0);
 
 // Mixed-precision ladder (split-bf16, three products, FP32 accumulation).
 // fit: choose the widest slab whose workspace fits ws_bytes (ws must be given);
@@ -114,6 +124,11 @@ size_t bf16x3_workspace_bytes(int o, int v, int naux);
 size_t bf16x3_workspace_bytes_min(int o, int v, int naux);  // one-block-pair slabs
 int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int v, int naux, double* R,
                void* ws, size_t ws_bytes, int shard, int nshards, hipStream_t s, bool fit = false);
+
+// The exchange-symmetric ladder (symmetric factors) in split bf16 with slabs of slab_bp
+// block pairs; B_vv [naux][v][v] contiguous.  Workspace allocated for the call.
+int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, double* R, long slab_bp,
+                   hipStream_t s);
 
 // Ladder argument checks shared by the entry points (status, error text set).
 int check_ladder_args(const double* B_vv, const double* tau, int o, int v, int naux, const double* R,

@@ -23,13 +23,13 @@ import numpy as np
 
 def build_dataset(shapes, per_system: int, seed: int, scale="naux", tol: float = 1e-8, log=None):
     """(X [N][8] float32, Y [N] float32, info) from converged systems: raw features of
-    amplitudes drawn with probability ~ t2_MP2^2 (with replacement) and their
-    relative corrections t2_CCSD / t2_MP2 - 1, clipped to [-3, 3]."""
+    amplitudes drawn with probability ~ t2_MP2^2 (with replacement; ri_mlp_sample, seed
+    `seed` + system number) and their relative corrections t2_CCSD / t2_MP2 - 1, clipped
+    to [-3, 3] (ri_mlp_targets).  Everything but the row gather runs in the library."""
     import torch
 
     from . import ccsd, mlp
     from .synthetic import draw_system
-    rng = np.random.default_rng(seed)
     Xs, Ys = [], []
     iters = []
     t0 = time.perf_counter()
@@ -45,13 +45,9 @@ def build_dataset(shapes, per_system: int, seed: int, scale="naux", tol: float =
                 log(f"  system {k} (o={o} v={v}) did not converge; skipped")
             continue
         iters.append(rep.iterations)
-        m = t2m.reshape(-1)
-        w = (m * m).cpu().numpy()
-        idx = rng.choice(m.numel(), size=per_system, p=w / w.sum())
-        idx_t = torch.from_numpy(idx).to("cuda")
-        r = (t2.reshape(-1)[idx_t] / m[idx_t] - 1.0).clamp(-3.0, 3.0)
-        Xs.append(X.index_select(0, idx_t).cpu().numpy())
-        Ys.append(r.cpu().numpy().astype(np.float32))
+        idx = mlp.sample(t2m, per_system, seed + k)
+        Xs.append(X.index_select(0, idx).cpu().numpy())
+        Ys.append(mlp.targets(t2.contiguous(), t2m, idx).cpu().numpy())
         if log and (k % 32 == 0 or k == len(shapes) - 1):
             log(f"  system {k + 1}/{len(shapes)} o={o} v={v}: {rep.iterations} iterations, "
                 f"{time.perf_counter() - t0:.1f} s elapsed")
@@ -63,29 +59,27 @@ def build_dataset(shapes, per_system: int, seed: int, scale="naux", tol: float =
 def train(X, Y, hidden=256, layers=2, epochs=30, batch=4096, lr=5e-4, seed=0, holdout=0.05, log=None):
     """Fit the network to (X, Y) with the library's training loop; returns (net, history).
 
-    Features are standardised and the target divided by its standard deviation
-    (both stored in the network); a held-out fraction measures the fit after each
-    epoch (history: held-out loss per epoch)."""
+    A held-out fraction (rows chosen by a seeded permutation) measures the fit after
+    each epoch (history: held-out loss per epoch).  The library fits the feature
+    standardisation and the output scale to the training rows (ri_mlp_fit_scaling),
+    stores them in the network and applies them (ri_mlp_standardize)."""
     import torch
 
     from . import mlp
     rng = np.random.default_rng(seed + 1)
     perm0 = rng.permutation(X.shape[0])
     nho = max(1, int(holdout * X.shape[0]))
-    ho, tr = perm0[:nho], perm0[nho:]
-    mean = X[tr].mean(axis=0).astype(np.float32)
-    std = X[tr].std(axis=0).astype(np.float32)
-    std[std <= 0] = 1.0
-    y_scale = float(Y[tr].std()) or 1.0
-    Xn = ((X - mean) / std).astype(np.float32)
-    Yn = (Y / y_scale).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    ho, tr = dev(perm0[:nho]), dev(perm0[nho:])
+    Xd, Yd = dev(X), dev(Y)
+    Xtr, Ytr = Xd.index_select(0, tr), Yd.index_select(0, tr)
     net = mlp.Net(X.shape[1], hidden, layers)
     net.init(seed)
-    net.set_scaling(mean, std, y_scale)
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    net.fit_scaling(Xtr, Ytr)
+    Xn, Yn = net.standardize(Xtr, Ytr)
+    Xh, Yh = net.standardize(Xd.index_select(0, ho), Yd.index_select(0, ho))
     t0 = time.perf_counter()
-    tl, vl = net.train(dev(Xn[tr]), dev(Yn[tr]), dev(Xn[ho]), dev(Yn[ho]), epochs=epochs, batch=batch, lr=lr,
-                       seed=seed + 2)
+    tl, vl = net.train(Xn, Yn, Xh, Yh, epochs=epochs, batch=batch, lr=lr, seed=seed + 2)
     if log:
         for ep in range(epochs):
             log(f"  epoch {ep + 1}/{epochs}: mean batch loss {tl[ep]:.4e}, held-out loss {vl[ep]:.4e} "

@@ -134,6 +134,30 @@ class Net:
                    "ri_mlp_guess")
         return t1, t2
 
+    def fit_scaling(self, X: torch.Tensor, Y: torch.Tensor, stream=None):
+        """Set the feature standardisation and output scale from the raw training data
+        (column means and deviations of X, deviation of Y; ri_mlp_fit_scaling)."""
+        n = X.shape[0]
+        _need(X, "X", (n, self.d_in), torch.float32)
+        _need(Y, "Y", (n,), torch.float32)
+        _lib.check(_lib.lib().ri_mlp_fit_scaling(self._h, X.data_ptr(), Y.data_ptr(), n, _stream(stream)),
+                   "ri_mlp_fit_scaling")
+
+    def standardize(self, X: torch.Tensor, Y: torch.Tensor | None = None, stream=None):
+        """(Xn, Yn) = ((X - mean) / std, Y / y_scale) with the network's scaling
+        (ri_mlp_standardize); Yn is None when Y is."""
+        n = X.shape[0]
+        _need(X, "X", (n, self.d_in), torch.float32)
+        Xn = torch.empty_like(X)
+        Yn = None
+        if Y is not None:
+            _need(Y, "Y", (n,), torch.float32)
+            Yn = torch.empty_like(Y)
+        _lib.check(_lib.lib().ri_mlp_standardize(self._h, X.data_ptr(), None if Y is None else Y.data_ptr(), n,
+                                                 Xn.data_ptr(), None if Yn is None else Yn.data_ptr(),
+                                                 _stream(stream)), "ri_mlp_standardize")
+        return Xn, Yn
+
     def save(self, path: str):
         _lib.check(_lib.lib().ri_mlp_save(self._h, path.encode()), "ri_mlp_save")
 
@@ -157,6 +181,30 @@ def features(B: torch.Tensor, eps: torch.Tensor, o: int, t2_mp2: torch.Tensor, s
     _lib.check(_lib.lib().ri_mlp_features(ctypes.byref(sy), t2_mp2.data_ptr(), X.data_ptr(), _stream(stream)),
                "ri_mlp_features")
     return X
+
+
+def sample(t2_mp2: torch.Tensor, n: int, seed: int, stream=None) -> torch.Tensor:
+    """n amplitude indices (int64, flat) drawn with probability ~ t2_MP2^2 (ri_mlp_sample)."""
+    if not t2_mp2.is_cuda or t2_mp2.dtype != torch.float64 or not t2_mp2.is_contiguous():
+        raise TypeError("t2_mp2 must be a contiguous FP64 device tensor")
+    idx = torch.empty(n, dtype=torch.int64, device=t2_mp2.device)
+    _lib.check(_lib.lib().ri_mlp_sample(t2_mp2.data_ptr(), t2_mp2.numel(), n, int(seed), idx.data_ptr(),
+                                        _stream(stream)), "ri_mlp_sample")
+    return idx
+
+
+def targets(t2_ccsd: torch.Tensor, t2_mp2: torch.Tensor, idx: torch.Tensor, clip: float = 3.0,
+            stream=None) -> torch.Tensor:
+    """Y[s] = clamp(t2_CCSD / t2_MP2 - 1, -clip, clip) at the flat indices idx (ri_mlp_targets)."""
+    for t, name in ((t2_ccsd, "t2_ccsd"), (t2_mp2, "t2_mp2")):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous FP64 device tensor")
+    if idx.dtype != torch.int64 or not idx.is_cuda or not idx.is_contiguous():
+        raise TypeError("idx must be a contiguous int64 device tensor")
+    Y = torch.empty(idx.numel(), dtype=torch.float32, device=idx.device)
+    _lib.check(_lib.lib().ri_mlp_targets(t2_ccsd.data_ptr(), t2_mp2.data_ptr(), idx.data_ptr(), idx.numel(),
+                                         float(clip), Y.data_ptr(), _stream(stream)), "ri_mlp_targets")
+    return Y
 
 
 def init_params(d_in: int = N_FEATURES, hidden: int = 256, layers: int = 2, seed: int = 0) -> np.ndarray:

@@ -88,17 +88,16 @@ def ppl_paper(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, stream=Non
     return R
 
 
-def ppl_sym(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, stream=None) -> torch.Tensor:
+def ppl_sym(B_vv: torch.Tensor, tau: torch.Tensor, R: torch.Tensor, precision="fp64", stream=None) -> torch.Tensor:
     """The same sum for factors symmetric in their two virtual indices, using the
-    exchange symmetry of the integral matrix to build about half of it (ri_ppl_sym),
-    FP64."""
+    exchange symmetry of the integral matrix to build about half of it (ri_ppl_sym_ex)."""
     naux, v = B_vv.shape[0], B_vv.shape[1]
     o = tau.shape[0]
     _need(B_vv, "B_vv", (naux, v, v))
     _need(tau, "tau", (o, o, v, v))
     _need(R, "R", (o, o, v, v))
-    _lib.check(_lib.lib().ri_ppl_sym(B_vv.data_ptr(), tau.data_ptr(), o, v, naux, R.data_ptr(), _stream(stream)),
-               "ri_ppl_sym")
+    _lib.check(_lib.lib().ri_ppl_sym_ex(B_vv.data_ptr(), tau.data_ptr(), o, v, naux, R.data_ptr(), _prec(precision),
+                                        _stream(stream)), "ri_ppl_sym")
     return R
 
 

@@ -87,6 +87,58 @@ def test_adam_steps_follow_the_oracle_trajectory():
     assert clear.sum() > 0.5 * theta.size
 
 
+def test_sampling_matches_oracle():
+    """ri_mlp_sample against the oracle's inverse-CDF sampler on the same SplitMix64
+    stream.  The running sums are formed in another order (chunks of 4096), so an index
+    may differ only where the threshold lies within rounding of a cumulative boundary;
+    there the device's pick must still bracket the threshold."""
+    from paper_1810_08142_amd import mlp
+    o, v = 3, 70  # 44100 amplitudes: eleven chunks and a ragged last one
+    t2m = draw_matrix((o, o, v, v), 41)
+    t2m[0, 0, :5, :] = 0.0  # zero weights are never drawn
+    n, seed = 20000, 77
+    got = host(mlp.sample(dev(t2m), n, seed))
+    ref, cum, u = om.sample_indices(t2m, n, seed)
+    diff = np.nonzero(got != ref)[0]
+    print(f"sampling: {diff.size} of {n} indices differ from the oracle's", flush=True)
+    for s_ in diff:
+        k = got[s_]
+        lo = cum[k - 1] if k > 0 else 0.0
+        assert lo - 1e-12 * cum[-1] <= u[s_] < cum[k] + 1e-12 * cum[-1]
+    assert diff.size <= 2
+    assert np.all(t2m.ravel()[got] != 0.0)
+
+
+def test_targets_and_scaling_match_oracle():
+    import torch
+    from paper_1810_08142_amd import mlp
+    shape = (2, 2, 9, 9)
+    t2m = draw_matrix(shape, 51)
+    t2c = t2m * (1.0 + 0.5 * draw_matrix(shape, 52))
+    t2c.ravel()[:3] = 20.0 * t2m.ravel()[:3]  # beyond the clip
+    idx = np.arange(0, t2m.size, 3, dtype=np.int64)
+    Y = host(mlp.targets(dev(t2c), dev(t2m), dev(idx)))
+    Yr = om.targets(t2c, t2m, idx).astype(np.float32)  # FP64 arithmetic, one rounding to FP32
+    assert np.array_equal(Y, Yr)
+    net = mlp.Net(8, 16, 1)
+    n = 20001  # three row chunks, ragged
+    X = (3.0 + 2.0 * draw_matrix((n, 8), 53)).astype(np.float32)
+    X[:, 6] = 1.5  # a constant column: std 1 by convention
+    Yv = (0.1 * draw_matrix(n, 54)).astype(np.float32)
+    net.fit_scaling(dev(X), dev(Yv))
+    mean, std, ys = net.get_scaling()
+    mr, sr, ysr = om.scaling(X.astype(np.float64), Yv.astype(np.float64))
+    np.testing.assert_allclose(mean, mr, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(std, sr, rtol=1e-6)
+    assert abs(ys - ysr) <= 1e-6 * ysr
+    Xn, Yn = net.standardize(dev(X), dev(Yv))
+    Xr = (X.astype(np.float64) - mean.astype(np.float64)) / std.astype(np.float64)
+    np.testing.assert_allclose(host(Xn), Xr, rtol=0, atol=1e-5)
+    np.testing.assert_allclose(host(Yn), Yv.astype(np.float64) / float(ys), rtol=1e-6, atol=1e-7)
+    Xn2, Yn2 = net.standardize(dev(X))
+    assert Yn2 is None and torch.equal(Xn2, Xn)
+
+
 def test_features_match_oracle():
     from paper_1810_08142_amd import mlp
     o, v, naux = 3, 13, 20

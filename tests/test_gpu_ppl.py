@@ -305,25 +305,26 @@ def test_paper_arrangement_chunks_do_not_change_result(monkeypatch):
     assert rel_max(outs[1], outs[0]) <= 1e-13 and rel_max(outs[2], outs[0]) <= 1e-13
 
 
-@pytest.mark.parametrize("o,v,naux,slabs,large", [
-    (1, 3, 2, 8, 0),        # one block pair: a single slab, no second product
-    (2, 17, 7, 8, 0),       # three block pairs, one per slab
-    (1, 50, 20, 3, 0),      # o = 1 (no antisymmetric part) over several slabs
-    (3, 33, 20, 3, 1),      # ragged slabs, second product on the large-tile GEMM kernel
-    (4, 40, 37, 8, 0),
-    (2, 50, 130, 4, 1),
-    (3, 70, 24, 1000, 0),   # one block pair per slab (15 slabs)
-    (5, 64, 40, 2, 0),      # v a multiple of 16, two slabs
-])
-def test_exchange_symmetric_form_matches_oracle(o, v, naux, slabs, large, monkeypatch):
+SYM_SHAPES = [  # (o, v, naux, slabs)
+    (1, 3, 2, 8),        # one block pair: a single slab, no second product
+    (2, 17, 7, 8),       # three block pairs, one per slab
+    (1, 50, 20, 3),      # o = 1 (no antisymmetric part) over several slabs
+    (3, 33, 20, 3),      # ragged slabs
+    (4, 40, 37, 8),
+    (2, 50, 130, 4),
+    (3, 70, 24, 1000),   # one block pair per slab (15 slabs)
+    (5, 64, 40, 2),      # v a multiple of 16, two slabs
+]
+
+
+@pytest.mark.parametrize("o,v,naux,slabs", SYM_SHAPES)
+def test_exchange_symmetric_form_matches_oracle(o, v, naux, slabs, monkeypatch):
     """ri_ppl_sym (half the build through the (ab) <-> (cd) exchange symmetry) gives the
     oracle's ladder to 1e-11 and ri_ppl's to rounding, for any slab schedule."""
     import torch
     ppl = _ppl()
-    print(f"ppl_sym o={o} v={v} naux={naux} slabs={slabs} large={large}", flush=True)
+    print(f"ppl_sym o={o} v={v} naux={naux} slabs={slabs}", flush=True)
     monkeypatch.setenv("RI_PPL_SYM_SLABS", str(slabs))
-    if large:
-        monkeypatch.setenv("RI_GEMM_LARGE_MIN_TILES", "1")
     s = draw_system(o, v, naux, seed=o * 100 + v + 7)
     B = np.ascontiguousarray(s.B_vv)
     T = draw_pair_symmetric(o, v, 11 + v, 0.01)
@@ -336,6 +337,31 @@ def test_exchange_symmetric_form_matches_oracle(o, v, naux, slabs, large, monkey
     Rt = _gpu_ladder(B, T, R0)
     assert rel_max(got - R0, Rt - R0) <= TOL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("o,v,naux,slabs", [SYM_SHAPES[i] for i in (1, 3, 5, 6, 7)])
+def test_exchange_symmetric_form_reduced_precision(o, v, naux, slabs, precision, monkeypatch):
+    """ri_ppl_sym_ex in FP32 and split bf16: within the split error bound 2e-4 L(|B|, |tau|)
+    of the oracle element by element (L: the oracle's ladder of the absolute values), and
+    exactly pair-symmetric."""
+    import torch
+    ppl = _ppl()
+    print(f"ppl_sym {precision} o={o} v={v} naux={naux} slabs={slabs}", flush=True)
+    monkeypatch.setenv("RI_PPL_SYM_SLABS", str(slabs))
+    s = draw_system(o, v, naux, seed=o * 100 + v + 9)
+    B = np.ascontiguousarray(s.B_vv)
+    T = draw_pair_symmetric(o, v, 17 + v, 0.01)
+    R = torch.zeros((o, o, v, v), dtype=torch.float64, device="cuda")
+    ppl.ppl_sym(dev(B), dev(T), R, precision=precision)
+    got = host(R)
+    ref = native.ppl(B, T)
+    bound = 2e-4 * native.ppl(np.abs(B), np.abs(T))
+    err = np.abs(got - ref)
+    print("max rel err", float(err.max() / np.abs(ref).max()), "max err/bound", float((err / bound).max()))
+    assert bool(np.all(err <= bound))
+    assert float(err.max()) > 0.0
+    assert np.array_equal(got, got.transpose(1, 0, 3, 2))
 
 
 def test_exchange_symmetric_form_checks_its_factors_and_arguments():
@@ -360,4 +386,5 @@ def test_exchange_symmetric_form_checks_its_factors_and_arguments():
     L = _lib.lib()
     assert L.ri_ppl_sym(None, T.data_ptr(), o, v, naux, R.data_ptr(), None) == 1
     assert L.ri_ppl_sym(B.data_ptr(), T.data_ptr(), o, v, naux, T.data_ptr(), None) == 2
+    assert L.ri_ppl_sym_ex(B.data_ptr(), T.data_ptr(), o, v, naux, R.data_ptr(), 7, None) == 1
     torch.cuda.synchronize()

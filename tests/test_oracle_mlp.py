@@ -109,3 +109,46 @@ def test_features_pair_symmetric_and_defined():
     want = [t2[i, j, a, b], t2[i, j, b, a], iajb, ibja, e[i] + e[j] - e[o + a] - e[o + b],
             (e[o + a] - e[o + b]) ** 2, (e[i] - e[j]) ** 2, math.sqrt(iaia * jbjb)]
     np.testing.assert_allclose(F[i, j, a, b], want, rtol=1e-13, atol=1e-16)
+
+
+def test_splitmix64_reproduces_the_published_sequence():
+    # the generator's reference output for state 0 (Vigna's splitmix64.c test values)
+    assert [mlp.splitmix64(0, c) for c in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                        0x06C45D188009454F]
+    u = mlp.sample_uniforms(1000, 9)
+    assert u.min() > 0.0 and u.max() < 1.0
+
+
+def test_sampler_inverse_cdf_hand_example():
+    # weights 1, 0, 3 (t2 = 1, 0, sqrt 3): cumulative 1, 1, 4; a threshold below 1
+    # picks index 0, one in [1, 4) picks index 2, and index 1 (zero weight) never
+    idx, cum, u = mlp.sample_indices(np.array([1.0, 0.0, math.sqrt(3.0)]), 400, 5)
+    np.testing.assert_allclose(cum, [1.0, 1.0, 4.0], rtol=1e-15)
+    assert np.array_equal(idx, np.where(u < 1.0, 0, 2))
+
+
+def test_sampler_frequencies_follow_the_squared_amplitudes():
+    rng = np.random.default_rng(31)
+    t = rng.standard_normal(7)
+    t[3] = 0.0
+    n = 60000
+    idx, _, _ = mlp.sample_indices(t, n, 123)
+    p = t**2 / np.sum(t**2)
+    freq = np.bincount(idx, minlength=7) / n
+    # binomial standard error sqrt(p (1 - p) / n) <= 0.0021; 5 sigma
+    assert np.all(np.abs(freq - p) <= 5 * np.sqrt(p * (1 - p) / n) + 1e-12)
+    assert freq[3] == 0.0
+
+
+def test_targets_and_scaling_definitions():
+    t2m = np.array([0.5, -0.25, 0.1, 2.0])
+    t2c = np.array([0.75, -0.25, 1.0, -10.0])
+    # 0.75/0.5 - 1 = 0.5; -0.25/-0.25 - 1 = 0; 1.0/0.1 - 1 = 9 -> clipped 3; -10/2 - 1 = -6 -> -3
+    np.testing.assert_array_equal(mlp.targets(t2c, t2m, [0, 1, 2, 3]), [0.5, 0.0, 3.0, -3.0])
+    X = np.array([[1.0, 5.0], [3.0, 5.0]])
+    Y = np.array([2.0, 6.0])
+    mean, std, ys = mlp.scaling(X, Y)
+    # column 0: mean 2, deviations +-1 -> std 1; column 1 constant -> std 1 by convention
+    np.testing.assert_array_equal(mean, [2.0, 5.0])
+    np.testing.assert_array_equal(std, [1.0, 1.0])
+    assert ys == 2.0
