@@ -64,15 +64,6 @@ __device__ inline f32x4_t mfma3(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t 
   c = mfma_bf16(al, bh, c);
   return mfma_bf16(ah, bh, c);
 }
-// The same with the two cross terms in the mirrored order, used for (ad|bc): (ad|bc)
-// for (a, b) then accumulates the products of (ac|bd) for (b, a) in the same order.
-// (a == b occurs only in diagonal ab block pairs, whose (ad|bc) tile is read back as
-// the transpose of the (ac|bd) tile, so V- = (ac|bd) - (ad|bc) is exactly zero there.)
-__device__ inline f32x4_t mfma3_mirror(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t bl, f32x4_t c) {
-  c = mfma_bf16(al, bh, c);
-  c = mfma_bf16(ah, bl, c);
-  return mfma_bf16(ah, bh, c);
-}
 
 // LDS swizzles.  A ds_read_b128 is conflict-free when every group of 8 lanes
 // (32 banks) -- or of 16 lanes (64 banks) -- covers distinct 16-byte bank groups.
@@ -355,40 +346,55 @@ __device__ __forceinline__ void build_diag_body(const uint16_t* __restrict__ Bh,
 // g = w >> 2 (0: (ac|bd), 1: (ad|bc)), for 4 c by 8 d: c = 8h + 4(q >> 1) + i,
 // d = 8(q & 1) + j with q = w & 3.  Per Q step a wave then reads 24 fragments for 96
 // MFMAs instead of 32 (both integrals for 4 x 4 pairs), with the same 128 accumulator
-// registers.  After the Q loop the (ad|bc) waves pass their tiles through LDS (the
-// tiles of both integrals share one lane layout, element (a, b) at lane b + 16(a/4)),
-// and the (ac|bd) waves write W+- for their 32 pairs into the slots of the slot order
-// above.  The launch covers cd block pairs pcd0 .. nbp-1; diagonal ab block pairs exit
-// (the diagonal kernel builds them).
-// grid ((nbp - pcd0)*2, slab_pairs), block 512
-// Workgroup order: the tiles (ab pair, cd half) are dealt in groups of ga ab pairs by
-// gc cd halves (consecutive in both, so a group's factor rows and columns span few
-// blocks), groups round-robin to the eight XCDs in dispatch order (workgroup id mod 8),
-// so the workgroups one XCD runs together share most of their factor data in its L2.
-// One-dimensional grid of 8 * ceil(groups / 8) * ga * gc workgroups; false for the
-// padding ones.
-__device__ inline bool group_tile(long ncdh, long npairs, int ga, int gc, long& cdh, long& pab) {
-  const long L = blockIdx.x, x = L & 7, p = L >> 3, G = static_cast<long>(ga) * gc;
+// registers.  Both integrals run one instruction stream: a wave's first operand is its
+// c fragment, its second the d fragment; the (ac|bd) waves read the c rows at the a
+// columns and the d rows at the b columns and so hold element (a, b) of each tile,
+// the (ad|bc) waves read the c rows at the b columns and the d rows at the a columns
+// and hold the transposed tile, element (b, a).  After the Q loop the (ad|bc) waves
+// pass their tiles through LDS, transposed back on the way, and the (ac|bd) waves
+// write W+- for their 32 pairs into the slots of the slot order above.  The (ad|bc)
+// products of (a, b) are then those of the (ac|bd) tile of (b, a) in the same order,
+// so where both exist for one (a, b, c, d) they agree bit for bit.  The launch covers
+// cd block pairs pcd0 .. nbp-1; diagonal ab block pairs exit (the diagonal kernel
+// builds them).  Block 512.
+// Workgroup order: the workgroups of one ab block pair and a square tile of T x T cd
+// block pairs (c blocks by d blocks, both halves: 2T^2 workgroups, the tiles counted
+// triangularly from the tile row of pcd0's d block) form a group; consecutive groups
+// (cd tiles fastest, then ga ab block pairs) go round-robin to the eight XCDs in
+// dispatch order (workgroup id mod 8), so the workgroups one XCD runs together read
+// the factor rows of 2T blocks.  One-dimensional grid of 8 * ceil(groups / 8) * ga *
+// 2T^2 workgroups; false for those that cover no pair (c block > d block, cd pairs
+// before pcd0, the padding).
+__device__ inline bool group_tile(int nb, long pcd0, long npairs, int ga, int T, long& pab, long& pcd, int& half) {
+  const long GT = 2L * T * T;
+  const long L = blockIdx.x, x = L & 7, p = L >> 3, G = static_cast<long>(ga) * GT;
   const long gi = (p / G) * 8 + x, r = p % G;
-  const long ngc = (ncdh + gc - 1) / gc, nga = (npairs + ga - 1) / ga;
-  if (gi >= ngc * nga) return false;
-  pab = (gi / ngc) * ga + r / gc;
-  cdh = (gi % ngc) * gc + r % gc;
-  return pab < npairs && cdh < ncdh;
+  int C0, D0;
+  tri_decode(pcd0, C0, D0);
+  const long nT = (nb + T - 1) / T, k0 = D0 / T, t0 = k0 * (k0 + 1) / 2;
+  const long ntile = nT * (nT + 1) / 2 - t0, nga = (npairs + ga - 1) / ga;
+  if (gi >= ntile * nga) return false;
+  pab = (gi / ntile) * ga + r / GT;
+  int tj, tk;
+  tri_decode(t0 + gi % ntile, tj, tk);
+  const int rr = static_cast<int>(r % GT);
+  half = rr & 1;
+  const int C = tj * T + (rr >> 1) % T, D = tk * T + (rr >> 1) / T;
+  if (pab >= npairs || C > D || D >= nb) return false;
+  pcd = static_cast<long>(D) * (D + 1) / 2 + C;
+  return pcd >= pcd0;
 }
 
 __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
                                                  int Qp, int vp, long slab0, long K, int want_minus, long pcd0,
-                                                 long npairs, int ga, int gc,
+                                                 long npairs, int ga, int gt,
                                                  uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
                                                  uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
   __shared__ u32x4_t lds[3 * SLOT];
   static_assert(3 * SLOT * 16 >= 4 * 32 * 4 * 64 * 4, "the ring holds the exchanged (ad|bc) tiles");
-  const long nbp = static_cast<long>(vp / TB) * (vp / TB + 1) / 2;
-  long cdh, pab_loc;
-  if (!group_tile(2 * (nbp - pcd0), npairs, ga, gc, cdh, pab_loc)) return;
-  const int half = static_cast<int>(cdh & 1);
-  const long pcd = pcd0 + (cdh >> 1);
+  long pab_loc, pcd;
+  int half;
+  if (!group_tile(vp / TB, pcd0, npairs, ga, gt, pab_loc, pcd, half)) return;
   int Cb, Db, Ab, Bb;
   tri_decode(pcd, Cb, Db);
   tri_decode(slab0 + pab_loc, Ab, Bb);
@@ -438,8 +444,9 @@ __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh
     for (int j = 0; j < 8; ++j) o[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
   const int nsteps = Qp / QC;
-  // in a diagonal cd block pair the slots with c > d carry zero amplitudes: with c in
-  // the upper half and d in the lower one every pair of the wave has c > d
+  // in a diagonal cd block pair the slots with c > d carry zero amplitudes: with c in the upper half and d in the
+  // lower one every pair of the wave has c > d.  Such a wave runs the same products (a
+  // branch around them costs the loop its schedule) and stores zeros.
   const bool zero_w = Cb == Db && half == 1 && (q & 1) == 0;
   {
     auto compute = [&](int s0, int s1) {
@@ -454,21 +461,21 @@ __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int hl = 0; hl < 2; ++hl) cf[i][hl] = frag(xc0 + i, hl, ec);
-      if (g == 0) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const bf16x8_t dh = frag(xd0 + j, 0, ed), dl = frag(xd0 + j, 1, ed);
+      for (int j = 0; j < 8; ++j) {
+        const bf16x8_t dh = frag(xd0 + j, 0, ed), dl = frag(xd0 + j, 1, ed);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) o[i][j] = mfma3(cf[i][0], cf[i][1], dh, dl, o[i][j]);
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const bf16x8_t dh = frag(xd0 + j, 0, ed), dl = frag(xd0 + j, 1, ed);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) o[i][j] = mfma3_mirror(dh, dl, cf[i][0], cf[i][1], o[i][j]);
-        }
+        for (int i = 0; i < 4; ++i) o[i][j] = mfma3(cf[i][0], cf[i][1], dh, dl, o[i][j]);
       }
+      // issue order: the c fragments and the first d pair, then per d the 12 products
+      // with the next d pair's reads ahead of them
+      __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
     };
     u32x4_t sa[6], sb[6];
     gload(sa, 0, 0);
@@ -488,7 +495,7 @@ __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh
         lstore(sa, sf);
         if (st + 2 < nsteps) gload(sa, 0, st + 2);
       }
-      if (!zero_w) compute(s0, s1);
+      compute(s0, s1);
       __syncthreads();
       if (more) {
         lstore(sb, s0);
@@ -503,16 +510,27 @@ __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh
   // (ac|bd) wave q reads them back in the same order (the loop ended with a barrier
   // after every wave's last fragment read)
   float* xb = reinterpret_cast<float*>(lds);
+  const int m_l = 4 * (lane >> 4), n_l = lane & 15;  // a lane holds element (m_l + r, n_l)
   if (g == 1) {
+    // element (m, n) of tile (q, i, j) at float m*16 + 4((n >> 2) ^ ((m >> 2) & 3)) + (n & 3)
+    // of the tile's 1 KB: conflict-free stores here and loads below
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 8; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) xb[(((q * 4 + i) * 8 + j) * 4 + r) * 64 + lane] = o[i][j][r];
+        for (int r = 0; r < 4; ++r) {
+          const int m = m_l + r;
+          xb[((q * 4 + i) * 8 + j) * 256 + m * 16 + 4 * ((n_l >> 2) ^ ((m >> 2) & 3)) + (n_l & 3)] = o[i][j][r];
+        }
   }
   __syncthreads();
   if (g == 1) return;
+  // (ad|bc) at this lane's (a, b) = (m_l + r, n_l): element (n_l, m_l + r) of the stored tile
+  auto xval = [&](int i, int j, int r) -> float {
+    const int n = m_l + r;
+    return xb[((q * 4 + i) * 8 + j) * 256 + n_l * 16 + 4 * ((n >> 2) ^ ((n_l >> 2) & 3)) + (n & 3)];
+  };
 
   // epilogue: (c, d) = (8h + 4(q>>1) + i, 8(q&1) + j) sits in slot
   // h*128 + ow*16 + i*4 + (j & 3) with ow = 4(q>>1) + 2(q&1) + (j>>2) (the slot order of
@@ -534,7 +552,7 @@ __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh
 #pragma unroll
           for (int j2 = 0; j2 < 4; ++j2) {
             const int i = 2 * hh + i2, j = 4 * jb + j2;
-            const float v1 = o[i][j][r], v2 = xb[(((q * 4 + i) * 8 + j) * 4 + r) * 64 + lane];
+            const float v1 = zero_w ? 0.f : o[i][j][r], v2 = zero_w ? 0.f : xval(i, j, r);
             split_f32(v1 + v2, ph[i2 * 4 + j2], pl[i2 * 4 + j2]);
             split_f32(v1 - v2, mh[i2 * 4 + j2], ml[i2 * 4 + j2]);
           }
@@ -562,10 +580,10 @@ __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh
 }
 __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
                                                       int Qp, int vp, long slab0, long K, int want_minus, long pcd0,
-                                                      long npairs, int ga, int gc, uint16_t* __restrict__ Wph,
+                                                      long npairs, int ga, int gt, uint16_t* __restrict__ Wph,
                                                       uint16_t* __restrict__ Wpl, uint16_t* __restrict__ Wmh,
                                                       uint16_t* __restrict__ Wml) {
-  build_split_body(Bh, Bl, Qp, vp, slab0, K, want_minus, pcd0, npairs, ga, gc, Wph, Wpl, Wmh, Wml);
+  build_split_body(Bh, Bl, Qp, vp, slab0, K, want_minus, pcd0, npairs, ga, gt, Wph, Wpl, Wmh, Wml);
 }
 __global__ __launch_bounds__(512) void build_w_bf16x3_diag(const uint16_t* __restrict__ Bh,
                                                            const uint16_t* __restrict__ Bl, int Qp, int vp, long slab0,
@@ -864,15 +882,21 @@ static void launch_contract(int ntw, const CArgs& a, hipStream_t s) {
 }
 
 // Off-diagonal build of the slab's ab block pairs [slab0, slab0 + npairs) against cd
-// block pairs pcd0 .. nbp-1, in the grouped workgroup order (groups of one ab block
-// pair by 32 cd halves: measured best of 1x32, 2x16, 4x8, 8x4 at o=48 v=768 naux=2304).
-constexpr int GROUP_AB = 1, GROUP_CD = 32;
+// block pairs pcd0 .. nbp-1, in the grouped workgroup order: one ab block pair by a
+// 4 x 4 tile of cd block pairs, i.e. 32 workgroups, one per CU of an XCD (at o=48
+// v=768 naux=2304 2% faster than 2 x 2 or 8 x 8 tiles and than runs of 32 consecutive
+// cd halves).
+constexpr int GROUP_AB = 1, GROUP_T = 4;
 static void launch_build(const uint16_t* Bh, const uint16_t* Bl, const MPlan& p, long slab0, long npairs, long pcd0,
                          uint16_t* Wph, uint16_t* Wpl, uint16_t* Wmh, uint16_t* Wml, hipStream_t s) {
-  const long ngroups = ((2 * (p.nbp - pcd0) + GROUP_CD - 1) / GROUP_CD) * ((npairs + GROUP_AB - 1) / GROUP_AB);
-  const long nwg = (ngroups + 7) / 8 * 8 * GROUP_AB * GROUP_CD;
+  const long nb = p.vp / TB, nT = (nb + GROUP_T - 1) / GROUP_T;
+  int C0, D0;
+  tri_decode(pcd0, C0, D0);
+  const long k0 = D0 / GROUP_T, ntile = nT * (nT + 1) / 2 - k0 * (k0 + 1) / 2;
+  const long ngroups = ntile * ((npairs + GROUP_AB - 1) / GROUP_AB);
+  const long nwg = (ngroups + 7) / 8 * 8 * GROUP_AB * 2L * GROUP_T * GROUP_T;
   build_w_bf16x3<<<dim3(static_cast<unsigned>(nwg)), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K, p.pm > 0 ? 1 : 0,
-                                                                   pcd0, npairs, GROUP_AB, GROUP_CD, Wph, Wpl, Wmh,
+                                                                   pcd0, npairs, GROUP_AB, GROUP_T, Wph, Wpl, Wmh,
                                                                    Wml);
 }
 
