@@ -325,6 +325,11 @@ int ri_mlp_set_scaling(ri_mlp* net, const float* mean, const float* std, float y
 int ri_mlp_get_scaling(const ri_mlp* net, float* mean, float* std, float* y_scale);
 /* y[n] = net(X) for device X [n][d_in] (already standardised), FP32. */
 int ri_mlp_forward(ri_mlp* net, const float* X, long n, float* y, void* stream);
+/* The same y without keeping the hidden activations: every 64 rows go through all
+ * layers in one workgroup, in the operation order of ri_mlp_forward (equal results
+ * bit for bit).  Needs d_in a multiple of 4 and hidden a multiple of 16, both at most
+ * 256 (else RI_E_ARG); allocates nothing. */
+int ri_mlp_infer(const ri_mlp* net, const float* X, long n, float* y, void* stream);
 /* Loss and its gradient (device FP32 [num_params]; NULL uses internal storage) on a
  * batch of n <= 2^24 rows; the loss is written to *loss_host when not NULL
  * (synchronises stream).  Deterministic (fixed reduction order). */
@@ -391,8 +396,10 @@ int ri_mlp_targets(const double* t2_ccsd, const double* t2_mp2, const long* idx,
 int ri_mlp_fit_scaling(ri_mlp* net, const float* X, const float* Y, long n, void* stream);
 int ri_mlp_standardize(const ri_mlp* net, const float* X, const float* Y, long n, float* Xn, float* Yn,
                        void* stream);
-/* Learned guess: t1 = 0, t2 = t2_MP2 * (1 + y_scale * net), pair-symmetrised (FP64
- * outputs).  The network must have 8 inputs. */
+/* Learned guess: t1 = 0, t2 = t2_MP2 * (1 + y_scale * net) (FP64 outputs).  The network
+ * runs on the amplitudes with i <= j and its value goes to both (i, j, a, b) and
+ * (j, i, b, a); on i == j the two orders of (a, b) are averaged.  The network must have 8
+ * inputs; with d_in and hidden as ri_mlp_infer needs it runs through that kernel. */
 int ri_mlp_guess(ri_mlp* net, const ri_system* sys, double* t1, double* t2, void* stream);
 /* Binary file with sizes, scaling and parameters. */
 int ri_mlp_save(const ri_mlp* net, const char* path);

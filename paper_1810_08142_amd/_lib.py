@@ -87,6 +87,7 @@ _SIGS = [
     ("ri_mlp_set_scaling", _c.c_int, [_c.c_void_p, _fltp, _fltp, _c.c_float]),
     ("ri_mlp_get_scaling", _c.c_int, [_c.c_void_p, _fltp, _fltp, _fltp]),
     ("ri_mlp_forward", _c.c_int, [_c.c_void_p, _dp, _c.c_long, _dp, _dp]),
+    ("ri_mlp_infer", _c.c_int, [_c.c_void_p, _dp, _c.c_long, _dp, _dp]),
     ("ri_mlp_gradient", _c.c_int, [_c.c_void_p, _dp, _dp, _c.c_long, _dp, _fltp, _dp]),
     ("ri_mlp_train_step", _c.c_int, [_c.c_void_p, _dp, _dp, _c.c_long, _c.c_float, _fltp, _dp]),
     ("ri_mlp_init", _c.c_int, [_c.c_void_p, _c.c_ulonglong, _dp]),

@@ -303,14 +303,215 @@ __global__ void features_kernel(const double* __restrict__ gov, const double* __
   }
 }
 
-// t2 = t2_MP2 * (1 + scale * y), rows row0 .. row0 + n
-__global__ void add_correction(double* t2, const double* __restrict__ t2m, long row0, long n,
-                               const float* __restrict__ y, float scale) {
+// The pair-symmetric half of the (i, j, a, b) set: rows [row0, row0 + n) of the
+// amplitudes with i <= j, pair p = j (j + 1) / 2 + i, row p v^2 + a v + b.
+__device__ inline long half_index(long r, int o, int v) {
+  const long vv = static_cast<long>(v) * v;
+  const long p = r / vv, ab = r - p * vv;
+  long j = static_cast<long>((sqrt(8.0 * static_cast<double>(p) + 1.0) - 1.0) * 0.5);
+  while ((j + 1) * (j + 2) / 2 <= p) ++j;
+  while (j * (j + 1) / 2 > p) --j;
+  const long i = p - j * (j + 1) / 2;
+  return (i * o + j) * vv + ab;
+}
+
+// Features of the half-set rows [row0, row0 + n) (see features_kernel).
+__global__ void features_half_kernel(const double* __restrict__ gov, const double* __restrict__ eps,
+                                     const double* __restrict__ t2, int o, int v, long row0, long n, Norm nm,
+                                     float* X) {
   const long r = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r < n) t2[row0 + r] = t2m[row0 + r] * (1.0 + static_cast<double>(scale) * static_cast<double>(y[r]));
+  if (r >= n) return;
+  const long idx = half_index(row0 + r, o, v);
+  const long vv = static_cast<long>(v) * v;
+  const int b = idx % v, a = (idx / v) % v;
+  const long ij = idx / vv;
+  const int j = ij % o, i = ij / o;
+  auto G = [&](int p, int x, int q, int y) { return gov[((static_cast<long>(p) * v + x) * o + q) * v + y]; };
+  const double ea = eps[o + a], eb = eps[o + b], ei = eps[i], ej = eps[j];
+  double f[NF];
+  f[0] = t2[idx];
+  f[1] = t2[ij * vv + static_cast<long>(b) * v + a];
+  f[2] = G(i, a, j, b);
+  f[3] = G(i, b, j, a);
+  f[4] = ei + ej - ea - eb;
+  f[5] = (ea - eb) * (ea - eb);
+  f[6] = (ei - ej) * (ei - ej);
+  f[7] = sqrt(G(i, a, i, a) * G(j, b, j, b));
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    float x = static_cast<float>(f[k]);
+    if (nm.on) x = (x - nm.mean[k]) * nm.inv_std[k];
+    X[r * NF + k] = x;
+  }
+}
+
+// t2[ijab] = t2[jiba] = t2_MP2[ijab] * (1 + scale * y) for the half-set rows
+__global__ void add_correction_half(double* t2, const double* __restrict__ t2m, int o, int v, long row0, long n,
+                                    const float* __restrict__ y, float scale) {
+  const long r = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const long idx = half_index(row0 + r, o, v);
+  const long vv = static_cast<long>(v) * v;
+  const long b = idx % v, a = (idx / v) % v, ij = idx / vv;
+  const long j = ij % o, i = ij / o;
+  const double val = t2m[idx] * (1.0 + static_cast<double>(scale) * static_cast<double>(y[r]));
+  t2[idx] = val;
+  if (i != j) t2[(j * o + i) * vv + b * v + a] = val;  // i == j: the row (b, a) writes that one
+}
+
+// y[r] = net(X[r]), r < n, without keeping activations: each workgroup takes IR = 64
+// rows through every layer.  The layer input sits in LDS, element (m, k) at
+// m * HMAX + (k ^ 4 (m & 15)).  A hidden layer's W arrives in chunks of WK rows, each
+// loaded into registers while the previous one is in use; in LDS element (k, c) with
+// c = 16 u + l sits at k * HMAX + 16 l + 4 (u4 ^ ((l >> 2) & 3)) + (u & 3), u4 = u >> 2,
+// so the sixteen B operands of a lane (one per output tile) are four 16-byte reads and
+// the reads of sixteen lanes hit distinct banks.  Wave w owns rows 16w .. 16w + 15 and
+// all outputs (NT = hidden / 16 tiles of the 16x16x4 FP32 MFMA; the output layer one
+// tile, its weight column read directly), summing k in steps of four from zero and
+// adding the bias, then tanh for the hidden layers: the operation order of forward()'s
+// GEMMs, so both give the same y bit for bit.  d_in a multiple of 4, at most HMAX.
+// grid ceil(n / IR), block 256.
+constexpr int IR = 64, HMAX = 256, WK = 8;
+template <int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void infer_kernel(const float* __restrict__ X, long n, int d_in, int layers,
+                                                    const float* __restrict__ params, float* __restrict__ y) {
+  constexpr int HID = 16 * NT, NQ = (NT + 3) / 4;  // 16-byte groups of a lane's B operands
+  constexpr int RUNS = WK * 16 * NQ, PER = (RUNS + 255) / 256;
+  __shared__ float sH[IR * HMAX];
+  __shared__ float sW[WK * HMAX];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int l16 = lane & 15, kq = lane >> 4, mrow = 16 * w + l16;
+  const long r0 = static_cast<long>(blockIdx.x) * IR;
+  auto hidx = [](int m, int k) { return m * HMAX + (k ^ (4 * (m & 15))); };
+  auto wrun = [](int k, int l, int u4) { return k * HMAX + 16 * l + 4 * (u4 ^ ((l >> 2) & 3)); };
+  for (int e = t; e < IR * d_in; e += 256) {
+    const int m = e / d_in, k = e - m * d_in;
+    sH[hidx(m, k)] = r0 + m < n ? X[(r0 + m) * d_in + k] : 0.f;
+  }
+  const float* Wl = params;
+  int fin = d_in;
+  for (int l = 0; l < layers; ++l) {
+    const float* bl = Wl + static_cast<size_t>(fin) * HID;
+    f32x4_t acc[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    // run q of a chunk: row k = q / (16 NQ), column l = (q / NQ) % 16, group u4 = q % NQ,
+    // i.e. W[k][16 (4 u4 + e) + l], e = 0..3 (zero beyond the layer)
+    f32x4_t pre[PER];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int p = 0; p < PER; ++p) {
+        const int q = t + 256 * p, k = q / (16 * NQ), lc = (q / NQ) % 16, u4 = q % NQ;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int u = 4 * u4 + e;
+          pre[p][e] = (q < RUNS && k0 + k < fin && u < NT) ? Wl[static_cast<size_t>(k0 + k) * HID + 16 * u + lc] : 0.f;
+        }
+      }
+    };
+    auto step = [&](int k0, int s4) {
+      const float a = sH[hidx(mrow, k0 + s4 + kq)];
+      f32x4_t bq[NQ];
+#pragma unroll
+      for (int g = 0; g < NQ; ++g) bq[g] = *reinterpret_cast<const f32x4_t*>(&sW[wrun(s4 + kq, l16, g)]);
+#pragma unroll
+      for (int u = 0; u < NT; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq[u >> 2][u & 3], acc[u], 0, 0, 0);
+    };
+    const int nch = (fin + WK - 1) / WK;
+    gload(0);
+    for (int ch = 0; ch < nch; ++ch) {
+      const int k0 = ch * WK;
+      __syncthreads();  // the layer input is complete; the previous chunk is consumed
+#pragma unroll
+      for (int p = 0; p < PER; ++p) {
+        const int q = t + 256 * p, k = q / (16 * NQ), lc = (q / NQ) % 16, u4 = q % NQ;
+        if (q < RUNS) *reinterpret_cast<f32x4_t*>(&sW[wrun(k, lc, u4)]) = pre[p];
+      }
+      __syncthreads();
+      if (ch + 1 < nch) gload(k0 + WK);
+      if (fin - k0 >= WK) {
+#pragma unroll
+        for (int s4 = 0; s4 < WK; s4 += 4) step(k0, s4);
+      } else {
+        for (int s4 = 0; s4 < fin - k0; s4 += 4) step(k0, s4);
+      }
+    }
+    __syncthreads();  // every wave has read the layer input
+    // D[m][c] at lane c + 16 (m / 4), element m % 4
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int c = 16 * u + l16;
+      const float bc = bl[c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float val = 1.f * acc[u][r];
+        val += bc;
+        sH[hidx(16 * w + 4 * kq + r, c)] = tanhf(val);
+      }
+    }
+    Wl = bl + HID;
+    fin = HID;
+  }
+  // output layer: one column of weights, read directly
+  __syncthreads();
+  const float* bl = Wl + fin;
+  f32x4_t acc = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < fin; k += 4) {
+    const float a = sH[hidx(mrow, k + kq)];
+    const float b = l16 == 0 ? Wl[k + kq] : 0.f;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+  if (l16 == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long m = r0 + 16 * w + 4 * kq + r;
+      float val = 1.f * acc[r];
+      val += bl[0];
+      if (m < n) y[m] = val;
+    }
+  }
 }
 
 inline unsigned nblk(long n) { return static_cast<unsigned>((n + 255) / 256); }
+
+inline bool infer_ok(const ri_mlp* net) {
+  return net->d_in % 4 == 0 && net->d_in <= HMAX && net->hidden % 16 == 0 && net->hidden <= HMAX;
+}
+
+template <int NT>
+static void launch_infer(const ri_mlp* net, const float* X, long n, float* y, hipStream_t s) {
+  infer_kernel<NT><<<static_cast<unsigned>((n + IR - 1) / IR), 256, 0, s>>>(X, n, net->d_in, net->layers,
+                                                                           net->params, y);
+}
+// y = net(X), n rows, by infer_kernel (chunks of 2^24 workgroups at most)
+int infer(const ri_mlp* net, const float* X, long n, float* y, hipStream_t s) {
+  const long step = static_cast<long>(IR) << 24;
+  for (long r0 = 0; r0 < n; r0 += step) {
+    const long nn = std::min(step, n - r0);
+    const float* Xc = X + r0 * net->d_in;
+    float* yc = y + r0;
+    switch (net->hidden / 16) {
+      case 1: launch_infer<1>(net, Xc, nn, yc, s); break;
+      case 2: launch_infer<2>(net, Xc, nn, yc, s); break;
+      case 3: launch_infer<3>(net, Xc, nn, yc, s); break;
+      case 4: launch_infer<4>(net, Xc, nn, yc, s); break;
+      case 5: launch_infer<5>(net, Xc, nn, yc, s); break;
+      case 6: launch_infer<6>(net, Xc, nn, yc, s); break;
+      case 7: launch_infer<7>(net, Xc, nn, yc, s); break;
+      case 8: launch_infer<8>(net, Xc, nn, yc, s); break;
+      case 9: launch_infer<9>(net, Xc, nn, yc, s); break;
+      case 10: launch_infer<10>(net, Xc, nn, yc, s); break;
+      case 11: launch_infer<11>(net, Xc, nn, yc, s); break;
+      case 12: launch_infer<12>(net, Xc, nn, yc, s); break;
+      case 13: launch_infer<13>(net, Xc, nn, yc, s); break;
+      case 14: launch_infer<14>(net, Xc, nn, yc, s); break;
+      case 15: launch_infer<15>(net, Xc, nn, yc, s); break;
+      default: launch_infer<16>(net, Xc, nn, yc, s); break;
+    }
+    RI_TRY(check_launch("infer_kernel"));
+  }
+  return RI_OK;
+}
 
 int gemm(GemmF32 g, int splits, hipStream_t s) {
   g.kper = (g.K + splits - 1) / splits;
@@ -1091,7 +1292,10 @@ int ri_mlp_guess(ri_mlp* net, const ri_system* sys, double* t1, double* t2, void
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int o = sys->o, v = sys->v;
   const long n = static_cast<long>(o) * o * v * v;
-  const long chunk = std::min(n, 1L << 20);
+  // the network sees the i <= j half of the amplitudes; t2 is pair-symmetric
+  const long nh = static_cast<long>(o) * (o + 1) / 2 * v * v;
+  const bool fused = mlp::infer_ok(net);
+  const long chunk = std::min(nh, fused ? (1L << 22) : (1L << 20));
   // gov [o][v][o][v], an unmodified copy of the MP2 t2 (features read it), X and y of a chunk
   const size_t gbytes = round_up(static_cast<size_t>(n) * sizeof(double), 256);
   void* buf = nullptr;
@@ -1107,18 +1311,39 @@ int ri_mlp_guess(ri_mlp* net, const ri_system* sys, double* t1, double* t2, void
     nm.inv_std[k] = 1.f / net->stdv[k];
   }
   int rc = cc::mp2_with_integrals(sys, gov, t1, t2m, s);
-  if (rc == RI_OK) rc = mlp::reserve(net, chunk, s);
-  for (long r0 = 0; r0 < n && rc == RI_OK; r0 += chunk) {
-    const long nn = std::min(chunk, n - r0);
-    mlp::features_kernel<<<mlp::nblk(nn), 256, 0, s>>>(gov, sys->eps, t2m, o, v, r0, nn, nm, X);
-    if ((rc = check_launch("features_kernel"))) break;
-    if ((rc = mlp::forward(net, X, nn, y, s))) break;
-    mlp::add_correction<<<mlp::nblk(nn), 256, 0, s>>>(t2, t2m, r0, nn, y, net->y_scale);
-    rc = check_launch("add_correction");
+  if (rc == RI_OK && !fused) rc = mlp::reserve(net, chunk, s);
+  for (long r0 = 0; r0 < nh && rc == RI_OK; r0 += chunk) {
+    const long nn = std::min(chunk, nh - r0);
+    mlp::features_half_kernel<<<mlp::nblk(nn), 256, 0, s>>>(gov, sys->eps, t2m, o, v, r0, nn, nm, X);
+    if ((rc = check_launch("features_half_kernel"))) break;
+    if (fused) {
+      rc = mlp::infer(net, X, nn, y, s);
+    } else {
+      rc = mlp::forward(net, X, nn, y, s);
+    }
+    if (rc) break;
+    mlp::add_correction_half<<<mlp::nblk(nn), 256, 0, s>>>(t2, t2m, o, v, r0, nn, y, net->y_scale);
+    rc = check_launch("add_correction_half");
   }
+  // averages the i == j entries over (a, b) <-> (b, a); the other pairs are equal already
   if (rc == RI_OK) rc = cc::symmetrize_pairs(t2, o, v, s);
   dev_free(buf, s);
   return rc;
+}
+
+int ri_mlp_infer(const ri_mlp* net, const float* X, long n, float* y, void* stream) {
+  clear_error();
+  RI_TRY(mlp::check_net(net, "ri_mlp_infer"));
+  if (!X || !y || n <= 0) {
+    set_error("ri_mlp_infer: invalid argument");
+    return RI_E_ARG;
+  }
+  if (!mlp::infer_ok(net)) {
+    set_error("ri_mlp_infer: needs d_in a multiple of 4 and hidden a multiple of 16, both at most %d (d_in %d, "
+              "hidden %d)", mlp::HMAX, net->d_in, net->hidden);
+    return RI_E_ARG;
+  }
+  return mlp::infer(net, X, n, y, static_cast<hipStream_t>(stream));
 }
 
 int ri_mlp_save(const ri_mlp* net, const char* path) {

@@ -1,7 +1,8 @@
 """Train and evaluate the learned starting guess for the doubles amplitudes.
 
-Training data: seeded synthetic systems (o ~ U{4..12}, v ~ U{40..120}, naux = 3v,
-Naux-normalised factor scale) converged by the GPU CCSD solver from the MP2 guess.
+Training data: seeded synthetic systems (256 with o ~ U{4..12}, v ~ U{40..120}, naux = 3v,
+Naux-normalised factor scale; --large adds systems with o ~ U{10..16}, v = 16 o)
+converged by the GPU CCSD solver from the MP2 guess.
 The network predicts the relative correction r = t2_CCSD / t2_MP2 - 1 (clipped to
 [-3, 3]); each system contributes amplitudes drawn with probability proportional to
 t2_MP2^2, so the mean squared error in r weighs every sample as its squared error in
@@ -134,6 +135,7 @@ def main(argv=None):
     t = sub.add_parser("train")
     t.add_argument("--out", required=True)
     t.add_argument("--systems", type=int, default=256)
+    t.add_argument("--large", type=int, default=0)
     t.add_argument("--per-system", type=int, default=8192)
     t.add_argument("--epochs", type=int, default=30)
     t.add_argument("--batch", type=int, default=4096)
@@ -153,7 +155,7 @@ def main(argv=None):
     from . import mlp
     from .synthetic import training_shapes
     if args.cmd == "train":
-        shapes = training_shapes()[:args.systems]
+        shapes = training_shapes(args.systems, large=args.large)
         log(f"[guess] building dataset from {len(shapes)} systems")
         X, Y, info = build_dataset(shapes, args.per_system, seed=12345, log=log)
         log(f"[guess] {X.shape[0]} samples from {info['systems']} systems in {info['seconds']:.1f} s")

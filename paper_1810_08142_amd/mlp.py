@@ -68,6 +68,14 @@ class Net:
         _lib.check(_lib.lib().ri_mlp_forward(self._h, X.data_ptr(), n, y.data_ptr(), _stream(stream)), "ri_mlp_forward")
         return y
 
+    def infer(self, X: torch.Tensor, stream=None) -> torch.Tensor:
+        """The forward values without keeping the hidden activations (ri_mlp_infer)."""
+        n = X.shape[0]
+        _need(X, "X", (n, self.d_in), torch.float32)
+        y = torch.empty(n, dtype=torch.float32, device=X.device)
+        _lib.check(_lib.lib().ri_mlp_infer(self._h, X.data_ptr(), n, y.data_ptr(), _stream(stream)), "ri_mlp_infer")
+        return y
+
     def gradient(self, X: torch.Tensor, Y: torch.Tensor, stream=None):
         n = X.shape[0]
         _need(X, "X", (n, self.d_in), torch.float32)

@@ -126,13 +126,19 @@ CONFIGS = {
 }
 
 
-def training_shapes(count: int = 256, seed: int = 999):
-    """(o, v, naux, seed) of the learned-guess training systems: o ~ U{4..12},
-    v ~ U{40..120}, naux = 3v, seeds 1000, 1001, ..."""
+def training_shapes(count: int = 256, seed: int = 999, large: int = 0):
+    """(o, v, naux, seed) of the learned-guess training systems: `count` small ones with
+    o ~ U{4..12}, v ~ U{40..120}, naux = 3v, seeds 1000, 1001, ...; then `large` ones at
+    the occupied/virtual ratio of the o=24 v=384 case, o ~ U{10..16}, v = 16 o,
+    naux = 3v, seeds 5000, 5001, ..."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
         o = int(rng.integers(4, 13))
         v = int(rng.integers(40, 121))
         out.append((o, v, 3 * v, 1000 + k))
+    rng = np.random.default_rng(seed + 1)
+    for k in range(large):
+        o = int(rng.integers(10, 17))
+        out.append((o, 16 * o, 48 * o, 5000 + k))
     return out

@@ -150,6 +150,60 @@ def test_features_match_oracle():
     assert np.all(np.abs(X - ref) <= 1e-6 * scale + 1e-12)
 
 
+@pytest.mark.parametrize("d_in,hidden,layers,n", [(8, 256, 2, 1000), (8, 64, 3, 4097), (4, 16, 1, 63),
+                                                    (8, 48, 2, 65)])
+def test_infer_equals_forward_bit_for_bit(d_in, hidden, layers, n):
+    """The one-kernel inference keeps forward's operation order: equal y bit for bit
+    (ragged row counts, 1-3 hidden layers, widths that are and are not multiples of 64)."""
+    net, theta = _net(d_in, hidden, layers, seed=hidden + 7 * layers)
+    X = draw_matrix((n, d_in), 17).astype(np.float32)
+    yf = host(net.forward(dev(X)))
+    yi = host(net.infer(dev(X)))
+    assert np.array_equal(yf, yi)
+    yr, _ = om.forward(theta, X.astype(np.float64), d_in, hidden, layers)
+    assert np.abs(yi - yr).max() <= 1e-4 * max(1.0, np.abs(yr).max())
+
+
+def test_infer_rejects_unsupported_widths():
+    from paper_1810_08142_amd import _lib, mlp
+    net = mlp.Net(8, 20, 2)
+    with pytest.raises(_lib.RIError, match="ri_mlp_infer"):
+        net.infer(dev(np.zeros((4, 8), dtype=np.float32)))
+
+
+def test_guess_matches_oracle_on_the_pair_symmetric_half():
+    """The guess runs the network on the i <= j amplitudes and mirrors them to
+    (j, i, b, a); i == j averages the two orders of (a, b).  Oracle: features, the
+    network in FP64 and the same composition."""
+    from paper_1810_08142_amd import mlp
+    o, v, naux = 3, 21, 40
+    s = draw_system(o, v, naux, seed=961)
+    net, theta = _net(8, 64, 2, seed=11)
+    mean = np.array([0.0, 0.0, 0.01, 0.01, -2.0, 1.0, 0.1, 0.02], dtype=np.float32)
+    std = np.array([0.05, 0.05, 0.02, 0.02, 1.0, 2.0, 0.2, 0.03], dtype=np.float32)
+    ys = 0.05
+    net.set_scaling(mean, std, ys)
+    t1, t2 = net.guess(dev(s.B), dev(s.eps), o)
+    t2 = host(t2)
+    _, t2m, _ = oc.mp2(s.B, s.eps, o)
+    F = om.features(s.B, s.eps, o, t2m).reshape(-1, om.N_FEATURES)
+    Xn = (F - mean.astype(np.float64)) / std.astype(np.float64)
+    y, _ = om.forward(theta, Xn, 8, 64, 2)
+    val = (t2m * (1.0 + float(np.float32(ys)) * y.reshape(o, o, v, v)))
+    ref = np.empty_like(val)
+    for i in range(o):
+        for j in range(o):
+            if i < j:
+                ref[i, j] = val[i, j]
+            elif i > j:
+                ref[i, j] = val[j, i].T
+            else:
+                ref[i, i] = 0.5 * (val[i, i] + val[i, i].T)
+    assert np.abs(host(t1)).max() == 0.0
+    assert np.array_equal(t2, t2.transpose(1, 0, 3, 2))
+    assert np.abs(t2 - ref).max() <= 1e-5 * np.abs(t2m).max()
+
+
 def test_zero_network_gives_mp2_and_correction_is_applied():
     from paper_1810_08142_amd import mlp
     o, v, naux = 2, 11, 15
@@ -202,7 +256,8 @@ def test_training_reduces_loss():
 def test_trained_guess_cuts_iterations_on_held_out_system():
     """Train on 128 small synthetic systems with the GPU kernels, then solve the
     held-out o=24 v=384 Naux=1152 system from the MP2 and from the learned guess:
-    the learned start must reach the same solution in fewer iterations."""
+    the learned start must reach the same solution in fewer iterations, and with the
+    split-bf16 ladder and an FP64 polish in less wall time (network included)."""
     from paper_1810_08142_amd import guess
     from paper_1810_08142_amd.synthetic import training_shapes
     print("building training set", flush=True)
@@ -219,6 +274,11 @@ def test_trained_guess_cuts_iterations_on_held_out_system():
     # the same CCSD solution (several exist), reached in fewer iterations
     assert abs(res["delta_e_corr"]) <= 1e-8 and res["max_abs_delta_t2"] <= 1e-6
     assert res["learned_guess"]["iterations"] < res["mp2_guess"]["iterations"]
+    mix = guess.evaluate(net, "c5", precision="bf16x3", polish_residual=1e-6)
+    print(mix, flush=True)
+    assert mix["mp2_guess"]["converged"] and mix["learned_guess"]["converged"]
+    assert abs(mix["delta_e_corr"]) <= 1e-8 and mix["max_abs_delta_t2"] <= 1e-6
+    assert mix["learned_guess"]["seconds"] < mix["mp2_guess"]["seconds"]
 
 
 # SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), output c of the stream seeded
