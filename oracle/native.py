@@ -41,6 +41,8 @@ def lib():
                                        ctypes.c_int, dp]
         L.oracle_ppl_pairs.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -82,3 +84,7 @@ def ppl_pairs(B_vv: np.ndarray, tau: np.ndarray, pairs) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))

@@ -52,6 +52,16 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads of the parallel loops below (n >= 1); used to time the oracle on one core
+ * and on all cores. */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* R += L over all (a, b, i, j). */
 int oracle_ppl(const double* B_vv, const double* tau, int o, int v, int naux, double* R) {
     if (!B_vv || !tau || !R || o <= 0 || v <= 0 || naux <= 0) return 1;
