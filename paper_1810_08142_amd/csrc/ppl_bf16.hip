@@ -713,6 +713,117 @@ __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restric
       }
 }
 
+// The same product with a square-ish tile: 256 (m) x 64 NSUB (n), eight waves in two
+// rows by four columns; wave (wr, wc) owns rows 128 wr .. 128 wr + 127 and columns
+// 16 NSUB wc .. + 16 NSUB - 1 (8 x NSUB MFMA tiles), so per k step it reads 16 A and
+// 2 NSUB B fragments for 24 NSUB MFMAs (the row strips above read 4 and 2 NTW for 6 NTW).
+// LDS holds 16-byte runs [row][8 runs: hl 2 x run 4] as above, double-buffered, but
+// with run q of row m at q ^ ((m >> 1) & 7): the sixteen rows of one fragment read still
+// hit distinct bank groups, and the swizzle repeats every 16 rows, so the fragments of
+// different row tiles lie at constant offsets from one address.  Every tile sums its k
+// steps in the order of contract_bf16x3.  grid (ncol/(64 NSUB), rows/256, splits),
+// block 512
+template <int NSUB>
+__global__ __launch_bounds__(512) void contract2_bf16x3(const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
+                                                        long lda, const uint16_t* __restrict__ Th,
+                                                        const uint16_t* __restrict__ Tl, long ldb, long K, int ncol,
+                                                        float* __restrict__ C, long kz, long zs, int accum) {
+  constexpr int BM = 256, BN = 64 * NSUB, NT = 512;
+  constexpr int ARUNS = BM * 8, BRUNS = BN * 8, APER = ARUNS / NT, BPER = BRUNS / NT;
+  __shared__ u32x4_t sA[2 * ARUNS];
+  __shared__ u32x4_t sB[2 * BRUNS];
+  unsigned tx, ty;
+  xcd_tile(tx, ty);
+  const long n0 = static_cast<long>(tx) * BN, m0 = static_cast<long>(ty) * BM;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int wr = w >> 2, wc = w & 3;
+  const long k_lo = blockIdx.z * kz;
+  const long k_len = (K < k_lo + kz ? K : k_lo + kz) - k_lo;
+  C += blockIdx.z * zs;
+
+  // staging: run id t + 512 r is row t/8 + 64 r of the tile, with the thread's own hi/lo
+  // array and 8-element run; sw8 of the row does not depend on r
+  const int srow = t >> 3, shl = (t >> 2) & 1, srun = t & 3;
+  const uint16_t* ap = (shl ? Wl : Wh) + static_cast<size_t>(m0 + srow) * lda + k_lo + srun * 8;
+  const uint16_t* bp = (shl ? Tl : Th) + static_cast<size_t>(n0 + srow) * ldb + k_lo + srun * 8;
+  const size_t astep = static_cast<size_t>(64) * lda, bstep = static_cast<size_t>(64) * ldb;
+  auto sw = [](int m) { return (m >> 1) & 7; };
+  const int slo = srow * 8 + ((shl * 4 + srun) ^ sw(srow));  // + 512 r
+  const int fr = lane & 15, frun = lane >> 4;
+
+  f32x4_t acc[8][NSUB];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int u = 0; u < NSUB; ++u) acc[i][u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  const long nsteps = k_len / KB;
+  u32x4_t ra[APER], rb[BPER];
+#pragma unroll
+  for (int r = 0; r < APER; ++r) ra[r] = *reinterpret_cast<const u32x4_t*>(ap + r * astep);
+#pragma unroll
+  for (int r = 0; r < BPER; ++r) rb[r] = *reinterpret_cast<const u32x4_t*>(bp + r * bstep);
+#pragma unroll
+  for (int r = 0; r < APER; ++r) sA[slo + 512 * r] = ra[r];
+#pragma unroll
+  for (int r = 0; r < BPER; ++r) sB[slo + 512 * r] = rb[r];
+  __syncthreads();
+  for (long st = 0; st < nsteps; ++st) {
+    const int ab = (st & 1) * ARUNS, bb = (st & 1) * BRUNS;
+    const bool more = st + 1 < nsteps;
+    if (more) {
+      const size_t ko = static_cast<size_t>(st + 1) * KB;
+#pragma unroll
+      for (int r = 0; r < APER; ++r) ra[r] = *reinterpret_cast<const u32x4_t*>(ap + r * astep + ko);
+#pragma unroll
+      for (int r = 0; r < BPER; ++r) rb[r] = *reinterpret_cast<const u32x4_t*>(bp + r * bstep + ko);
+    }
+    bf16x8_t bh[NSUB], bl[NSUB];
+#pragma unroll
+    for (int u = 0; u < NSUB; ++u) {
+      const int row = wc * 16 * NSUB + u * 16 + fr;
+      bh[u] = __builtin_bit_cast(bf16x8_t, sB[bb + row * 8 + (frun ^ sw(fr))]);
+      bl[u] = __builtin_bit_cast(bf16x8_t, sB[bb + row * 8 + ((4 + frun) ^ sw(fr))]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int row = wr * 128 + i * 16 + fr;
+      const bf16x8_t ah = __builtin_bit_cast(bf16x8_t, sA[ab + row * 8 + (frun ^ sw(fr))]);
+      const bf16x8_t al = __builtin_bit_cast(bf16x8_t, sA[ab + row * 8 + ((4 + frun) ^ sw(fr))]);
+#pragma unroll
+      for (int u = 0; u < NSUB; ++u) acc[i][u] = mfma3(ah, al, bh[u], bl[u], acc[i][u]);
+    }
+    // issue order: the B fragments and the first A pair, then per A row tile its
+    // products with the next pair's reads ahead of them
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * NSUB + 2, 0);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 3 * NSUB, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 3 * NSUB, 0);
+    if (more) {
+      const int na = ((st + 1) & 1) * ARUNS, nbb = ((st + 1) & 1) * BRUNS;
+#pragma unroll
+      for (int r = 0; r < APER; ++r) sA[na + slo + 512 * r] = ra[r];
+#pragma unroll
+      for (int r = 0; r < BPER; ++r) sB[nbb + slo + 512 * r] = rb[r];
+    }
+    __syncthreads();
+  }
+  // D[m][n]: lane n + 16*(m/4), element m%4
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int u = 0; u < NSUB; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long row = m0 + wr * 128 + i * 16 + 4 * (lane >> 4) + r;
+        float* c = C + row * ncol + n0 + wc * 16 * NSUB + u * 16 + (lane & 15);
+        *c = accum ? *c + acc[i][u][r] : acc[i][u][r];
+      }
+}
+
 // ---------------------------------------------------------------- slot order
 // Tn[n][256 q + 16 x + y] = T[n][256 q + split_slot(x, y)]: packed tau with the slots of
 // every block pair in natural order (16-bit words; rows of K).  grid (K/256, rows), block 256
@@ -767,6 +878,7 @@ struct MPlan {
   int o, v, naux, nb, vp, Qp;
   long nbp, K;
   int po, pm, NP, NM, ntw_p, ntw_m;
+  int wide_p, wide_m;  // 1: contract2_bf16x3 with NSUB = ntw / 4 for that side
   long slab_bp, slab_M;
   size_t n_B, n_Tp, n_Tm, n_W, n_S, n_A;  // element counts
   long zrows_p, zrows_m;                   // largest splits x rows of one contraction launch
@@ -820,8 +932,25 @@ static bool make_mplan(int o, int v, int naux, MPlan& p, size_t fit_bytes = 0) {
   p.K = p.nbp * 256;
   p.po = o * (o + 1) / 2;
   p.pm = o * (o - 1) / 2;
-  pick_ntw(p.po, 9, CBM, p.ntw_p, p.NP);
-  pick_ntw(p.pm, 9, CBM, p.ntw_m, p.NM);
+  // per side: the 256 x 64 NSUB tiles (NSUB 4, 3 or 2, the fewest padded columns, ties
+  // to the wider) unless they pad to more columns than the row strips
+  auto pick = [](int ncols, int& ntw, int& padded, int& wide) {
+    int sntw, spad;
+    pick_ntw(ncols, 9, CBM, sntw, spad);
+    int tpad = 1 << 30, tntw = 16;
+    for (int ns : {4, 3, 2}) {
+      const int w = 64 * ns, pad = std::max(1, (ncols + w - 1) / w) * w;
+      if (pad < tpad) {
+        tpad = pad;
+        tntw = 4 * ns;
+      }
+    }
+    wide = tpad <= spad ? 1 : 0;
+    ntw = wide ? tntw : sntw;
+    padded = wide ? tpad : spad;
+  };
+  pick(p.po, p.ntw_p, p.NP, p.wide_p);
+  pick(p.pm, p.ntw_m, p.NM, p.wide_m);
   if (p.pm == 0) p.NM = 0;
   const int nw = p.pm > 0 ? 2 : 1;
   const long budget = env_long("RI_PPL_W_BYTES", 16L << 30);
@@ -867,7 +996,21 @@ static void launch_c(const CArgs& a, hipStream_t s) {
       a.Wh, a.Wl, a.lda, a.Th, a.Tl, a.ldb, a.K, a.ncol, a.C, a.kz, a.rows * a.ncol, a.accum);
 }
 
-static void launch_contract(int ntw, const CArgs& a, hipStream_t s) {
+template <int NSUB>
+static void launch_c2(const CArgs& a, hipStream_t s) {
+  contract2_bf16x3<NSUB><<<dim3(a.ncol / (64 * NSUB), a.rows / CBM, a.splits), 512, 0, s>>>(
+      a.Wh, a.Wl, a.lda, a.Th, a.Tl, a.ldb, a.K, a.ncol, a.C, a.kz, a.rows * a.ncol, a.accum);
+}
+
+static void launch_contract(int wide, int ntw, const CArgs& a, hipStream_t s) {
+  if (wide) {
+    switch (ntw) {
+      case 8: launch_c2<2>(a, s); break;
+      case 12: launch_c2<3>(a, s); break;
+      default: launch_c2<4>(a, s); break;
+    }
+    return;
+  }
   switch (ntw) {
     case 1: launch_c<1>(a, s); break;
     case 2: launch_c<2>(a, s); break;
@@ -990,10 +1133,10 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
       }
       {
         ProfScope ps(s, "contract_bf16x3", 2.0 * (le * pv * p.po + lt * pvm * p.pm));
-        launch_contract(p.ntw_p, CArgs{Wph, Wpl, p.K, Tph, Tpl, p.K, p.K, M, p.NP, S, zp, kzp, 0}, s);
+        launch_contract(p.wide_p, p.ntw_p, CArgs{Wph, Wpl, p.K, Tph, Tpl, p.K, p.K, M, p.NP, S, zp, kzp, 0}, s);
         if ((rc = check_launch("contract_bf16x3(+)"))) break;
         if (p.pm > 0) {
-          launch_contract(p.ntw_m, CArgs{Wmh, Wml, p.K, Tmh, Tml, p.K, p.K, M, p.NM, A, zm, kzm, 0}, s);
+          launch_contract(p.wide_m, p.ntw_m, CArgs{Wmh, Wml, p.K, Tmh, Tml, p.K, p.K, M, p.NM, A, zm, kzm, 0}, s);
           if ((rc = check_launch("contract_bf16x3(-)"))) break;
         }
       }
@@ -1114,10 +1257,10 @@ int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, d
       const size_t c0 = static_cast<size_t>(slab0) * 256;  // first cd slot built for the slab
       {
         ProfScope ps(s, "contract_bf16x3", 2.0 * (le * ce * p.po + lt * ct * p.pm));
-        launch_contract(p.ntw_p, CArgs{Wph + c0, Wpl + c0, p.K, Tph + c0, Tpl + c0, p.K, K1, M, p.NP, S, zp, kzp, 0}, s);
+        launch_contract(p.wide_p, p.ntw_p, CArgs{Wph + c0, Wpl + c0, p.K, Tph + c0, Tpl + c0, p.K, K1, M, p.NP, S, zp, kzp, 0}, s);
         if ((rc = check_launch("contract_bf16x3(+)"))) break;
         if (p.pm > 0) {
-          launch_contract(p.ntw_m, CArgs{Wmh + c0, Wml + c0, p.K, Tmh + c0, Tml + c0, p.K, K1, M, p.NM, A, zm, kzm, 0},
+          launch_contract(p.wide_m, p.ntw_m, CArgs{Wmh + c0, Wml + c0, p.K, Tmh + c0, Tml + c0, p.K, K1, M, p.NM, A, zm, kzm, 0},
                           s);
           if ((rc = check_launch("contract_bf16x3(-)"))) break;
         }
@@ -1143,11 +1286,11 @@ int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, d
         double le2, lt2, ld2;
         count_pairs(v, p1, p.nbp - p1, le2, lt2, ld2);
         ProfScope ps(s, "contract2_bf16x3", 2.0 * (le2 * le * p.po + lt2 * lt * p.pm));
-        launch_contract(p.ntw_p, CArgs{W2[0], W2[1], M, Tnph + c0, Tnpl + c0, p.K, M, rows2, p.NP,
+        launch_contract(p.wide_p, p.ntw_p, CArgs{W2[0], W2[1], M, Tnph + c0, Tnpl + c0, p.K, M, rows2, p.NP,
                                        S2 + c1 * p.NP, 1, M, accum}, s);
         if ((rc = check_launch("contract2_bf16x3(+)"))) break;
         if (p.pm > 0) {
-          launch_contract(p.ntw_m, CArgs{W2[2], W2[3], M, Tnmh + c0, Tnml + c0, p.K, M, rows2, p.NM,
+          launch_contract(p.wide_m, p.ntw_m, CArgs{W2[2], W2[3], M, Tnmh + c0, Tnml + c0, p.K, M, rows2, p.NM,
                                          A2 + c1 * p.NM, 1, M, accum}, s);
           if ((rc = check_launch("contract2_bf16x3(-)"))) break;
         }
