@@ -69,7 +69,7 @@ def main(argv=None):
     ab.add_argument("--config", default="c2")
     ab.add_argument("--repeat", type=int, default=2)
     ab.add_argument("--forms", default="tau_pm,paper,sym",
-                    help="comma list of tau_pm, paper, sym, tau_pm_bf16x3, sym_bf16x3, sym_fp32")
+                    help="comma list of tau_pm, paper, sym, tau_pm_fp32, tau_pm_bf16x3, sym_bf16x3, sym_fp32")
     sh = sub.add_parser("shard")
     sh.add_argument("--config", default="c4")
     sh.add_argument("--nshards", type=int, default=8)
@@ -216,6 +216,7 @@ def _ablation(args):
     forms = {"tau_pm": (lambda R: ppl.ppl(B_vv, tau, R), ppl.flops(o, v, naux)),
              "paper": (lambda R: ppl.ppl_paper(B_vv, tau, R), ppl.paper_flops(o, v, naux)),
              "sym": (lambda R: ppl.ppl_sym(B_vv, tau, R), ppl.sym_flops(o, v, naux)),
+             "tau_pm_fp32": (lambda R: ppl.ppl(B_vv, tau, R, precision="fp32"), ppl.flops(o, v, naux)),
              "tau_pm_bf16x3": (lambda R: ppl.ppl(B_vv, tau, R, precision="bf16x3"), ppl.flops(o, v, naux)),
              "sym_bf16x3": (lambda R: ppl.ppl_sym(B_vv, tau, R, precision="bf16x3"), ppl.sym_flops(o, v, naux)),
              "sym_fp32": (lambda R: ppl.ppl_sym(B_vv, tau, R, precision="fp32"), ppl.sym_flops(o, v, naux))}
