@@ -339,8 +339,10 @@ def test_exchange_symmetric_form_matches_oracle(o, v, naux, slabs, monkeypatch):
     torch.cuda.synchronize()
 
 
+# (16, 37, 29) and (48, 40, 24) reach the split path's 256 x 64k contraction tiles, in the
+# slab contractions and in the second products
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("o,v,naux,slabs", [SYM_SHAPES[i] for i in (1, 3, 5, 6, 7)])
+@pytest.mark.parametrize("o,v,naux,slabs", [SYM_SHAPES[i] for i in (1, 3, 5, 6, 7)] + [(16, 37, 29, 3), (48, 40, 24, 8)])
 def test_exchange_symmetric_form_reduced_precision(o, v, naux, slabs, precision, monkeypatch):
     """ri_ppl_sym_ex in FP32 and split bf16: within the split error bound 2e-4 L(|B|, |tau|)
     of the oracle element by element (L: the oracle's ladder of the absolute values), and

@@ -36,8 +36,12 @@ def _ladder(B_vv, tau, precision="bf16x3"):
 PRECS = ["bf16x3", "fp32"]
 
 
+# (16, 37, 29): the tau- contraction (120 pairs) takes the 256 x 128 tiles, tau+ (136) the
+# row strips; (48, 40, 24): tau+ (1176 pairs) the 256 x 256 and tau- (1128) the 256 x 192
+# tiles, as at o=48 v=768 naux=2304
 @pytest.mark.parametrize("precision", PRECS)
-@pytest.mark.parametrize("o,v,naux", [(1, 3, 2), (2, 17, 7), (3, 33, 20), (4, 24, 96), (5, 40, 37), (2, 50, 130)])
+@pytest.mark.parametrize("o,v,naux", [(1, 3, 2), (2, 17, 7), (3, 33, 20), (4, 24, 96), (5, 40, 37), (2, 50, 130),
+                                      (16, 37, 29), (48, 40, 24)])
 def test_mixed_within_split_error_bound(o, v, naux, precision):
     print(f"{precision} o={o} v={v} naux={naux}", flush=True)
     s = draw_system(o, v, naux, seed=900 + v)
