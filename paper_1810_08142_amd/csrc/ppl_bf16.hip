@@ -9,8 +9,9 @@
 // with packed tau+-, unpack the mirrored entries into the FP64 R.
 //
 // Layouts (bf16 stored as 16-bit words):
-//   Bh/Bl [c][a][Q]        factors, Q contiguous (padded to 32): one 16-byte run holds
-//                          the 8 consecutive Q a lane feeds to one MFMA
+//   Bh/Bl [c][Q/32][a][32] factors in Q tiles of 32 (Q padded to 32): one 16-byte run
+//                          holds the 8 consecutive Q a lane feeds to one MFMA, and the
+//                          16 columns of one block read in a Q step are one 1 KB run
 //   Th/Tl [ij][slot]       packed tau+- (or tau-), slots contiguous
 //   Wh/Wl [ab slot][slot]  build output, already split, slots contiguous
 // Within a cd block pair the 256 slots are ordered so that the 16 (c, d) pairs one
@@ -80,7 +81,7 @@ __host__ __device__ inline void slot_cd(int slot, int& c_in, int& d_in) {
 }
 
 // ---------------------------------------------------------------- split relayout
-// Bh/Bl[c][a][Q] from B[q][a][c] at B + q*qs + a*rs + c (zero padded).
+// Bh/Bl[c][Q/32][a][32] from B[q][a][c] at B + q*qs + a*rs + c (zero padded).
 // grid (Qp/32, vp/32, vp), block 256: one a, a 32 (Q) x 32 (c) tile
 __global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__ B, long qs, long rs, int v,
                                                       int naux, int vp, int Qp, uint16_t* __restrict__ Bh,
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__
     if (c >= vp) continue;  // vp is a multiple of 16, the tile of 32
     uint16_t hi, lo;
     split_f64(tile[tx][ty + 8 * r], hi, lo);
-    const size_t idx = (static_cast<size_t>(c) * vp + a) * Qp + q;
+    const size_t idx = ((static_cast<size_t>(c) * (Qp / 32) + blockIdx.x) * vp + a) * 32 + tx;
     Bh[idx] = hi;
     Bl[idx] = lo;
   }
@@ -188,12 +189,12 @@ __device__ __forceinline__ void build_diag_body(const uint16_t* __restrict__ Bh,
       const_cast<uint16_t*>(src + static_cast<size_t>(c_base + xt) * xs), 0, -1, 0x00020000);
   const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<uint16_t*>(src + static_cast<size_t>(d_base + xt) * xs), 0, -1, 0x00020000);
-  const int voff = (ag * Qp + run_t * 8) * 2;  // bytes
+  const int voff = (ag * 32 + run_t * 8) * 2;  // bytes within the Q tile
   const int xsb2 = static_cast<int>(xs * 4);  // bytes for two factor rows
   // LDS run of staging run r within its slot: x' = x mod 12 = 2(r mod 6) + xt
   const int l0 = xt * 256 + (hl_w * 32 + e_t) * 4 + (run_t ^ sw4(e_t));  // + 512 per run
   auto gload = [&](u32x4_t* dst, int h2, int step) {  // runs 6*h2 .. 6*h2 + 5
-    const int qb = step * QC * 2;  // bytes
+    const int qb = step * vp * QC * 2;  // bytes: one Q tile of vp columns per step
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int r = 6 * h2 + k;
@@ -413,11 +414,11 @@ __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh
       const_cast<uint16_t*>(src + static_cast<size_t>(c_base + xt) * xs), 0, -1, 0x00020000);
   const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<uint16_t*>(src + static_cast<size_t>(d_base + xt) * xs), 0, -1, 0x00020000);
-  const int voff = (ag * Qp + run_t * 8) * 2;
+  const int voff = (ag * 32 + run_t * 8) * 2;
   const int xsb2 = static_cast<int>(xs * 4);
   const int l0 = xt * 256 + (hl_w * 32 + e_t) * 4 + (run_t ^ sw4(e_t));
   auto gload = [&](u32x4_t* dst, int h2, int step) {
-    const int qb = step * QC * 2;
+    const int qb = step * vp * QC * 2;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int r = 6 * h2 + k;
