@@ -682,20 +682,62 @@ struct Plan {
   size_t bytes;
 };
 
+// Workgroups of the contraction kernel for ntw and the element size resident at once.
+template <typename T>
+static const void* contract_fn(int ntw) {
+  typedef void (*F)(const T*, const T*, long, long, int, T*, long, long);
+  F f;
+  if constexpr (sizeof(T) == 8) {
+    switch (ntw) {
+      case 1: f = contract_f64<1>; break;
+      case 2: f = contract_f64<2>; break;
+      case 3: f = contract_f64<3>; break;
+      case 4: f = contract_f64<4>; break;
+      case 5: f = contract_f64<5>; break;
+      case 6: f = contract_f64<6>; break;
+      case 7: f = contract_f64<7>; break;
+      case 8: f = contract_f64<8>; break;
+      case 9: f = contract_f64<9>; break;
+      default: f = contract_f64<10>; break;
+    }
+  } else {
+    switch (ntw) {
+      case 1: f = contract_f32<1>; break;
+      case 2: f = contract_f32<2>; break;
+      case 3: f = contract_f32<3>; break;
+      case 4: f = contract_f32<4>; break;
+      case 5: f = contract_f32<5>; break;
+      case 6: f = contract_f32<6>; break;
+      case 7: f = contract_f32<7>; break;
+      case 8: f = contract_f32<8>; break;
+      case 9: f = contract_f32<9>; break;
+      default: f = contract_f32<10>; break;
+    }
+  }
+  return reinterpret_cast<const void*>(f);
+}
+static long contract_slots(int ntw, size_t esize) {
+  return resident_wgs(esize == 8 ? contract_fn<double>(ntw) : contract_fn<float>(ntw), 256, 2);
+}
+
 // Splits of the contraction's k range for a launch of `rows` rows and 16*ntw-wide
-// column tiles: enough workgroups to fill the chip about three deep (the kernel's
-// occupancy), and enough that one split's slice of the packed amplitudes (K/z rows of
-// ncol elements) stays within RI_PPL_TAU_CHUNK_MB (default TAU_CHUNK_MB): every row
-// tile streams its split's whole slice, and the workgroups resident together work on
-// the same few splits (z is the slowest grid index), so a slice that fits the last-level
-// cache is fetched from HBM about once instead of once per row tile.  At least 32
-// chunks per split.  kz: summed indices per split.
+// column tiles: at least one full round of resident workgroups, and enough that one
+// split's slice of the packed amplitudes (K/z rows of ncol elements) stays within
+// RI_PPL_TAU_CHUNK_MB (default TAU_CHUNK_MB): every row tile streams its split's whole
+// slice, and the workgroups resident together work on the same few splits (z is the
+// slowest grid index), so a slice that fits the last-level cache is fetched from HBM
+// about once instead of once per row tile.  Then balanced so that the last round of
+// workgroups is not a few stragglers.  At least 32 chunks per split.  kz: summed indices
+// per split.
 static int contract_splits(int ncol, int ntw, long rows, long K, size_t esize, long& kz) {
   const long nwg = (ncol / (16 * ntw)) * (rows / CRM);
-  long z = (3 * 256 + nwg - 1) / nwg;
+  const long slots = contract_slots(ntw, esize);
+  long z = (slots + nwg - 1) / nwg;
   const double chunk = static_cast<double>(env_long("RI_PPL_TAU_CHUNK_MB", TAU_CHUNK_MB)) * 1048576.0;
   z = std::max(z, static_cast<long>(std::ceil(static_cast<double>(K) * ncol * esize / chunk)));
-  z = std::max(1L, std::min(z, K / (32 * KC)));
+  const long zmax = std::max(1L, K / (32 * KC));
+  z = std::max(1L, std::min(z, zmax));
+  z = balance_splits(nwg, slots, K, KC, z, zmax);
   kz = (K + z - 1) / z;
   kz = (kz + KC - 1) / KC * KC;
   return static_cast<int>((K + kz - 1) / kz);

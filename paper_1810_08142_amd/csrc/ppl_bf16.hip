@@ -858,18 +858,45 @@ __global__ __launch_bounds__(256) void transpose_u16(const uint16_t* __restrict_
 }
 
 // ---------------------------------------------------------------- host
+// Workgroups of the contraction kernel for (wide, ntw) resident at once on the device.
+static long contract_slots(int wide, int ntw) {
+  const void* f;
+  if (wide) {
+    f = ntw == 8    ? reinterpret_cast<const void*>(&contract2_bf16x3<2>)
+        : ntw == 12 ? reinterpret_cast<const void*>(&contract2_bf16x3<3>)
+                    : reinterpret_cast<const void*>(&contract2_bf16x3<4>);
+    return resident_wgs(f, 512, 1);
+  }
+  switch (ntw) {
+    case 1: f = reinterpret_cast<const void*>(&contract_bf16x3<1>); break;
+    case 2: f = reinterpret_cast<const void*>(&contract_bf16x3<2>); break;
+    case 3: f = reinterpret_cast<const void*>(&contract_bf16x3<3>); break;
+    case 4: f = reinterpret_cast<const void*>(&contract_bf16x3<4>); break;
+    case 5: f = reinterpret_cast<const void*>(&contract_bf16x3<5>); break;
+    case 6: f = reinterpret_cast<const void*>(&contract_bf16x3<6>); break;
+    case 7: f = reinterpret_cast<const void*>(&contract_bf16x3<7>); break;
+    case 8: f = reinterpret_cast<const void*>(&contract_bf16x3<8>); break;
+    default: f = reinterpret_cast<const void*>(&contract_bf16x3<9>); break;
+  }
+  return resident_wgs(f, CNT, 1);
+}
+
 // Splits of the contraction's k range for a launch of `rows` rows and 16*ntw-wide
-// column tiles: enough workgroups to fill the chip about two deep (the kernel's
-// occupancy), and enough that one split's slice of the packed amplitudes (hi and lo
-// words, ncol rows of K/z) stays within RI_PPL_TAU_CHUNK_MB (default TAU_CHUNK_MB), for the
-// reason given with the FP64 path's splits.  At least 32 steps per split.  kz: summed
-// indices per split.
-static int contract_splits(int ncol, int ntw, long rows, long K, long& kz) {
+// column tiles (wide: the 256 x 64 NSUB kernel): at least one full round of resident
+// workgroups, and enough that one split's slice of the packed amplitudes (hi and lo
+// words, ncol rows of K/z) stays within RI_PPL_TAU_CHUNK_MB (default TAU_CHUNK_MB), for
+// the reason given with the FP64 path's splits; then balanced so that the last round of
+// workgroups is not a few stragglers.  At least 32 steps per split.  kz: summed indices
+// per split.
+static int contract_splits(int wide, int ntw, int ncol, long rows, long K, long& kz) {
   const long nwg = (ncol / (16 * ntw)) * (rows / CBM);
-  long z = (2 * 256 + nwg - 1) / nwg;
+  const long slots = contract_slots(wide, ntw);
+  long z = (slots + nwg - 1) / nwg;
   const double chunk = static_cast<double>(env_long("RI_PPL_TAU_CHUNK_MB", TAU_CHUNK_MB)) * 1048576.0;
   z = std::max(z, static_cast<long>(std::ceil(static_cast<double>(K) * ncol * 4.0 / chunk)));
-  z = std::max(1L, std::min(z, K / (32 * KB)));
+  const long zmax = std::max(1L, K / (32 * KB));
+  z = std::max(1L, std::min(z, zmax));
+  z = balance_splits(nwg, slots, K, KB, z, zmax);
   kz = (K + z - 1) / z;
   kz = (kz + KB - 1) / KB * KB;
   return static_cast<int>((K + kz - 1) / kz);
@@ -887,12 +914,13 @@ struct MPlan {
 };
 
 // Largest splits x rows over the slab sizes of plan p (the full slab and the last).
-static long max_split_rows(const MPlan& p, int ncol, int ntw) {
+static long max_split_rows(const MPlan& p, int wide, int ncol, int ntw) {
   if (ncol == 0) return 0;
   long kz;
   const long last = p.nbp - (p.nbp - 1) / p.slab_bp * p.slab_bp;
   long best = 0;
-  for (long rows : {p.slab_M, last * 256}) best = std::max(best, contract_splits(ncol, ntw, rows, p.K, kz) * rows);
+  for (long rows : {p.slab_M, last * 256})
+    best = std::max(best, contract_splits(wide, ntw, ncol, rows, p.K, kz) * rows);
   return best;
 }
 
@@ -903,8 +931,8 @@ static void size_mplan(MPlan& p) {
   p.n_Tp = static_cast<size_t>(p.NP) * p.K;
   p.n_Tm = static_cast<size_t>(p.NM) * p.K;
   p.n_W = static_cast<size_t>(p.slab_M) * p.K;
-  p.zrows_p = max_split_rows(p, p.NP, p.ntw_p);
-  p.zrows_m = max_split_rows(p, p.NM, p.ntw_m);
+  p.zrows_p = max_split_rows(p, p.wide_p, p.NP, p.ntw_p);
+  p.zrows_m = max_split_rows(p, p.wide_m, p.NM, p.ntw_m);
   p.n_S = static_cast<size_t>(p.zrows_p) * p.NP;
   p.n_A = static_cast<size_t>(p.zrows_m) * p.NM;
   size_t b = 0;
@@ -1119,8 +1147,8 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
       int dy0, ndiag;
       diag_pairs(slab0, npairs, dy0, ndiag);
       long kzp = 0, kzm = 0;
-      const int zp = contract_splits(p.NP, p.ntw_p, M, p.K, kzp);
-      const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, p.K, kzm) : 1;
+      const int zp = contract_splits(p.wide_p, p.ntw_p, p.NP, M, p.K, kzp);
+      const int zm = p.pm > 0 ? contract_splits(p.wide_m, p.ntw_m, p.NM, M, p.K, kzm) : 1;
       {  // off-diagonal and diagonal ab block pairs in two launches
         ProfScope ps(s, "build_w_bf16x3", 2.0 * naux * vv * (le - ld));
         launch_build(Bh, Bl, p, slab0, npairs, 0, Wph, Wpl, Wmh, Wml, s);
@@ -1253,8 +1281,8 @@ int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, d
         if ((rc = check_launch("build_w_bf16x3_diag"))) break;
       }
       long kzp = 0, kzm = 0;
-      const int zp = contract_splits(p.NP, p.ntw_p, M, K1, kzp);
-      const int zm = p.pm > 0 ? contract_splits(p.NM, p.ntw_m, M, K1, kzm) : 1;
+      const int zp = contract_splits(p.wide_p, p.ntw_p, p.NP, M, K1, kzp);
+      const int zm = p.pm > 0 ? contract_splits(p.wide_m, p.ntw_m, p.NM, M, K1, kzm) : 1;
       const size_t c0 = static_cast<size_t>(slab0) * 256;  // first cd slot built for the slab
       {
         ProfScope ps(s, "contract_bf16x3", 2.0 * (le * ce * p.po + lt * ct * p.pm));

@@ -70,6 +70,40 @@ __device__ inline void xcd_tile(unsigned& tx, unsigned& ty) {
   ty = tile / gx;
 }
 
+// Workgroups of kernel f (block threads each) resident on the current device at once:
+// blocks per CU by the runtime's occupancy rule (registers, LDS, waves) times the CU
+// count, or 256 * dflt_per_cu where the runtime gives no answer (no device).
+inline long resident_wgs(const void* f, int block, int dflt_per_cu) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, block, 0) == hipSuccess && cus > 0 && per > 0)
+    return static_cast<long>(per) * cus;
+  (void)hipGetLastError();  // leave no error behind for the next launch check
+  return 256L * dflt_per_cu;
+}
+
+// Split count for a launch of nwg workgroups per split, `slots` of which run at once,
+// over K summed indices taken `step` at a time.  The launch lasts about
+// ceil(nwg z / slots) rounds of one split's ceil(K / z) indices (rounded up to `step`):
+// a last round of a few workgroups costs as much as a full one.  Among z in
+// [z0, min(zmax, max(2 z0, z0 + 8))] the smallest whose modelled duration is within 3%
+// of the least is taken, since every split adds a partial output to write and reduce.
+inline long balance_splits(long nwg, long slots, long K, long step, long z0, long zmax) {
+  auto cost = [&](long z) {
+    long kz = (K + z - 1) / z;
+    kz = (kz + step - 1) / step * step;
+    const long zz = (K + kz - 1) / kz;  // splits launched
+    return static_cast<double>((nwg * zz + slots - 1) / slots) * static_cast<double>(kz);
+  };
+  const long hi = std::min(zmax, std::max(2 * z0, z0 + 8));
+  double best = cost(z0);
+  for (long z = z0 + 1; z <= hi; ++z) best = std::min(best, cost(z));
+  for (long z = z0; z <= hi; ++z)
+    if (cost(z) <= best * 1.03) return z;
+  return z0;
+}
+
 inline long env_long(const char* name, long dflt) {
   const char* s = getenv(name);
   if (!s || !*s) return dflt;
