@@ -586,6 +586,9 @@ __global__ __launch_bounds__(256) void contract_rows_f32(const float* __restrict
 // S and A are FP64 (FP64 path) or FP32 (mixed paths); R accumulates in FP64.  S and
 // A may come as zp (zm) partial sums over k, zs (zsm) elements apart, added here in
 // order.  perm: the rows of a block pair are in the split path's slot order.
+// The kernel is bound by memory latency unless many loads are in flight: a thread sums
+// its 16 rows of one column together (16 loads per split), and reads the R entries of
+// four columns before it writes them back.
 // grid (slab_pairs, ceil(po/16)), block 256
 template <class T>
 __global__ __launch_bounds__(256) void unpack_kernel(const T* __restrict__ S, const T* __restrict__ A,
@@ -600,51 +603,92 @@ __global__ __launch_bounds__(256) void unpack_kernel(const T* __restrict__ S, co
   const int po = o * (o + 1) / 2;
   const int lam0 = blockIdx.y * NG;
   const size_t row0 = static_cast<size_t>(blockIdx.x) * 256;
-  for (int r = 0; r < 16; ++r) {
-    const int slot = r * 16 + (t >> 4), cc = t & 15, lam = lam0 + cc;
-    const int srow = perm ? split_slot(r, t >> 4) : slot;
-    double s = 0.0, x = 0.0;
-    if (lam < po) {
-      int i, j;
-      tri_decode(lam, i, j);
-      const size_t is = (row0 + srow) * NP + lam;
-      for (int z = 0; z < zp; ++z) s += static_cast<double>(S[z * zsp + is]);
-      // the antisymmetric part vanishes at a == b (V-^{aa}_{cd} = (ac|ad) - (ad|ac)); rows
-      // that sum it from separately rounded integrals are not read, so R stays exactly
-      // pair-symmetric
-      if (i < j && !(Ab == Bb && r == (t >> 4))) {
-        const size_t ia = (row0 + srow) * NM + j * (j - 1) / 2 + i;
-        for (int z = 0; z < zm; ++z) x += static_cast<double>(A[z * zsm + ia]);
-      }
+  {
+    // column lam = lam0 + cc of rows r * 16 + rr (slot order), r = 0..15
+    // Loads are unconditional (a lane without work reads a valid neighbouring column
+    // and drops the value), so that they issue back to back.
+    const int cc = t & 15, rr = t >> 4, lam = lam0 + cc;
+    const bool lv = lam < po;
+    const int lamc = lv ? lam : po - 1;
+    int i, j;
+    tri_decode(lamc, i, j);
+    // the antisymmetric part vanishes at a == b (V-^{aa}_{cd} = (ac|ad) - (ad|ac)); rows
+    // that sum it from separately rounded integrals are not read, so R stays exactly
+    // pair-symmetric
+    const bool anti = lv && i < j;
+    const int ja = i < j ? j * (j - 1) / 2 + i : (j > 0 ? j * (j - 1) / 2 + j - 1 : 0);
+    auto srow = [&](int r) { return static_cast<size_t>(perm ? split_slot(r, rr) : r * 16 + rr); };
+    double s[16], x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s[r] = x[r] = 0.0;
+    for (int z = 0; z < zp; ++z) {
+      const T* Sz = S + z * zsp;
+      T u[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) u[r] = Sz[(row0 + srow(r)) * NP + lamc];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[r] += static_cast<double>(u[r]);
     }
-    sS[slot][cc] = s;
-    sA[slot][cc] = x;
+    for (int z = 0; NM > 0 && z < zm; ++z) {
+      const T* Az = A + z * zsm;
+      T u[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) u[r] = Az[(row0 + srow(r)) * NM + ja];
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        x[r] += anti && !(Ab == Bb && r == rr) ? static_cast<double>(u[r]) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      sS[r * 16 + rr][cc] = s[r];
+      sA[r * 16 + rr][cc] = x[r];
+    }
   }
   __syncthreads();
   const size_t vv = static_cast<size_t>(v) * v;
-  for (int cc = 0; cc < NG; ++cc) {
-    const int lam = lam0 + cc;
-    if (lam >= po) break;
-    int i, j;
-    tri_decode(lam, i, j);
-    double* Rij = R + (static_cast<size_t>(i) * o + j) * vv;
-    double* Rji = R + (static_cast<size_t>(j) * o + i) * vv;
-    {  // a <= b: rows contiguous in b
-      const int a_in = t >> 4, b_in = t & 15;
-      const int a = Ab * TB + a_in, b = Bb * TB + b_in;
-      if (a < v && b < v && (Ab < Bb || a_in <= b_in)) {
-        const double s = sS[a_in * 16 + b_in][cc], x = sA[a_in * 16 + b_in][cc];
-        Rij[static_cast<size_t>(a) * v + b] += s + x;
-        if (i != j) Rji[static_cast<size_t>(a) * v + b] += s - x;
+  const int hi = t >> 4, lo = t & 15;
+  // (a, b) with a <= b, rows contiguous in b; and the mirrors (b, a) with a < b, rows
+  // contiguous in a
+  const int a1 = Ab * TB + hi, b1 = Bb * TB + lo, a2 = Ab * TB + lo, b2 = Bb * TB + hi;
+  const bool ok1 = a1 < v && b1 < v && (Ab < Bb || hi <= lo);
+  const bool ok2 = a2 < v && b2 < v && (Ab < Bb || lo < hi);
+  const size_t e1 = static_cast<size_t>(a1) * v + b1, e2 = static_cast<size_t>(b2) * v + a2;
+  const int s1 = hi * 16 + lo, s2 = lo * 16 + hi;
+  for (int c0 = 0; c0 < NG; c0 += 4) {
+    double *Rij[4], *Rji[4];
+    bool val[4], off[4];
+    double q11[4], q12[4], q21[4], q22[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int lam = lam0 + c0 + k;
+      val[k] = lam < po;
+      int i = 0, j = 0;
+      if (val[k]) tri_decode(lam, i, j);
+      off[k] = i != j;  // R_ji is another element than R_ij
+      Rij[k] = R + (static_cast<size_t>(i) * o + j) * vv;
+      Rji[k] = R + (static_cast<size_t>(j) * o + i) * vv;
+      q11[k] = q12[k] = q21[k] = q22[k] = 0.0;
+      if (val[k] && ok1) {
+        q11[k] = Rij[k][e1];
+        if (off[k]) q12[k] = Rji[k][e1];
+      }
+      if (val[k] && ok2) {
+        q21[k] = Rij[k][e2];
+        if (off[k]) q22[k] = Rji[k][e2];
       }
     }
-    {  // mirrors with a < b: rows contiguous in a
-      const int b_in = t >> 4, a_in = t & 15;
-      const int a = Ab * TB + a_in, b = Bb * TB + b_in;
-      if (a < v && b < v && (Ab < Bb || a_in < b_in)) {
-        const double s = sS[a_in * 16 + b_in][cc], x = sA[a_in * 16 + b_in][cc];
-        Rij[static_cast<size_t>(b) * v + a] += s - x;
-        if (i != j) Rji[static_cast<size_t>(b) * v + a] += s + x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int cc = c0 + k;
+      if (val[k] && ok1) {
+        const double sv = sS[s1][cc], xv = sA[s1][cc];
+        Rij[k][e1] = q11[k] + (sv + xv);
+        if (off[k]) Rji[k][e1] = q12[k] + (sv - xv);
+      }
+      if (val[k] && ok2) {
+        const double sv = sS[s2][cc], xv = sA[s2][cc];
+        Rij[k][e2] = q21[k] + (sv - xv);
+        if (off[k]) Rji[k][e2] = q22[k] + (sv + xv);
       }
     }
   }
