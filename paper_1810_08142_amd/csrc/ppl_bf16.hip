@@ -12,8 +12,10 @@
 //   Bh/Bl [c][Q/32][a][32] factors in Q tiles of 32 (Q padded to 32): one 16-byte run
 //                          holds the 8 consecutive Q a lane feeds to one MFMA, and the
 //                          16 columns of one block read in a Q step are one 1 KB run
-//   Th/Tl [ij][slot]       packed tau+- (or tau-), slots contiguous
-//   Wh/Wl [ab slot][slot]  build output, already split, slots contiguous
+//   Th/Tl [slot/32][ij][32]       packed tau+- (or tau-) in tiles of 32 slots
+//   Wh/Wl [slot/32][ab slot][32]  build output, already split, in tiles of 32 slots
+// The contraction reads one tile (32 slots of a 256-row block, 16 KB per array) per k
+// step as one contiguous run.
 // Within a cd block pair the 256 slots are ordered so that the 16 (c, d) pairs one
 // wave of the build owns are consecutive: slot = half*128 + wave*16 + i*4 + j with
 // c = 8*half + 4*(wave>>2) + i, d = 4*(wave&3) + j.  A lane then stores its 16 results
@@ -106,10 +108,10 @@ __global__ __launch_bounds__(256) void split_b_kernel(const double* __restrict__
 }
 
 // ---------------------------------------------------------------- split pack
-// Th/Tl[col][pcd*256 + slot]: sign > 0 tau+ (with the 1/2 on c == d) over i<=j columns,
-// sign < 0 tau- over i<j columns; both from the pair-symmetric part of tau.
-// grid (nbp, ncol), block 256
-__global__ __launch_bounds__(256) void pack_tau_bf16_kernel(const double* __restrict__ tau, int o, int v, long K,
+// Th/Tl[k/32][col][k%32] with k = pcd*256 + slot: sign > 0 tau+ (with the 1/2 on c == d)
+// over i<=j columns, sign < 0 tau- over i<j columns; both from the pair-symmetric part of
+// tau.  grid (nbp, ncol), block 256
+__global__ __launch_bounds__(256) void pack_tau_bf16_kernel(const double* __restrict__ tau, int o, int v,
                                                             int sign, uint16_t* __restrict__ Th,
                                                             uint16_t* __restrict__ Tl) {
   int Cb, Db;
@@ -138,7 +140,8 @@ __global__ __launch_bounds__(256) void pack_tau_bf16_kernel(const double* __rest
   }
   uint16_t hi, lo;
   split_f64(val, hi, lo);
-  const size_t idx = static_cast<size_t>(col) * K + static_cast<size_t>(blockIdx.x) * 256 + slot;
+  const size_t k = static_cast<size_t>(blockIdx.x) * 256 + slot;
+  const size_t idx = (k / KB * gridDim.y + col) * KB + k % KB;
   Th[idx] = hi;
   Tl[idx] = lo;
 }
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(256) void pack_tau_bf16_kernel(const double* __rest
 // grid ((nbp - pcd0)*2, diagonal pairs), block 512
 constexpr int SLOT = 12 * 2 * 32 * 4;  // runs per LDS slot (48 KB)
 __device__ __forceinline__ void build_diag_body(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
-                                                  int Qp, int vp, long slab0, long K, int want_minus, int diag_y0,
+                                                  int Qp, int vp, long slab0, long wts, int want_minus, int diag_y0,
                                                   long pcd0, uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
                                                   uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
   __shared__ u32x4_t lds[3 * SLOT];
@@ -326,7 +329,8 @@ __device__ __forceinline__ void build_diag_body(const uint16_t* __restrict__ Bh,
         h[k] = static_cast<uint32_t>(ph[2 * k]) | (static_cast<uint32_t>(ph[2 * k + 1]) << 16);
         l[k] = static_cast<uint32_t>(pl[2 * k]) | (static_cast<uint32_t>(pl[2 * k + 1]) << 16);
       }
-      const size_t at = row * K + slot0 + 8 * hh;
+      const size_t k = slot0 + 8 * hh;
+      const size_t at = k / KB * wts + row * KB + k % KB;
       *reinterpret_cast<u32x4_t*>(Wph + at) = h;
       *reinterpret_cast<u32x4_t*>(Wpl + at) = l;
       if (want_minus) {
@@ -387,7 +391,7 @@ __device__ inline bool group_tile(int nb, long pcd0, long npairs, int ga, int T,
 }
 
 __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
-                                                 int Qp, int vp, long slab0, long K, int want_minus, long pcd0,
+                                                 int Qp, int vp, long slab0, long wts, int want_minus, long pcd0,
                                                  long npairs, int ga, int gt,
                                                  uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
                                                  uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
@@ -563,7 +567,8 @@ __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh
           h[k] = static_cast<uint32_t>(ph[2 * k]) | (static_cast<uint32_t>(ph[2 * k + 1]) << 16);
           l[k] = static_cast<uint32_t>(pl[2 * k]) | (static_cast<uint32_t>(pl[2 * k + 1]) << 16);
         }
-        const size_t at = row * K + slot0 + 8 * hh;
+        const size_t k = slot0 + 8 * hh;
+        const size_t at = k / KB * wts + row * KB + k % KB;
         *reinterpret_cast<u32x4_t*>(Wph + at) = h;
         *reinterpret_cast<u32x4_t*>(Wpl + at) = l;
         if (want_minus) {
@@ -580,22 +585,24 @@ __device__ __forceinline__ void build_split_body(const uint16_t* __restrict__ Bh
   }
 }
 __global__ __launch_bounds__(512) void build_w_bf16x3(const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl,
-                                                      int Qp, int vp, long slab0, long K, int want_minus, long pcd0,
+                                                      int Qp, int vp, long slab0, long wts, int want_minus, long pcd0,
                                                       long npairs, int ga, int gt, uint16_t* __restrict__ Wph,
                                                       uint16_t* __restrict__ Wpl, uint16_t* __restrict__ Wmh,
                                                       uint16_t* __restrict__ Wml) {
-  build_split_body(Bh, Bl, Qp, vp, slab0, K, want_minus, pcd0, npairs, ga, gt, Wph, Wpl, Wmh, Wml);
+  build_split_body(Bh, Bl, Qp, vp, slab0, wts, want_minus, pcd0, npairs, ga, gt, Wph, Wpl, Wmh, Wml);
 }
 __global__ __launch_bounds__(512) void build_w_bf16x3_diag(const uint16_t* __restrict__ Bh,
                                                            const uint16_t* __restrict__ Bl, int Qp, int vp, long slab0,
-                                                           long K, int want_minus, int diag_y0, long pcd0,
+                                                           long wts, int want_minus, int diag_y0, long pcd0,
                                                            uint16_t* __restrict__ Wph, uint16_t* __restrict__ Wpl,
                                                            uint16_t* __restrict__ Wmh, uint16_t* __restrict__ Wml) {
-  build_diag_body(Bh, Bl, Qp, vp, slab0, K, want_minus, diag_y0, pcd0, Wph, Wpl, Wmh, Wml);
+  build_diag_body(Bh, Bl, Qp, vp, slab0, wts, want_minus, diag_y0, pcd0, Wph, Wpl, Wmh, Wml);
 }
 
 // ---------------------------------------------------------------- contract
-// C[m][n] (+)= sum_k W[m][k] T[n][k] (both split; W rows lda, T rows ldb apart); tile
+// C[m][n] (+)= sum_k W[m][k] T[n][k], both split and stored in tiles of KB k: element
+// (m, k) of W at (k / KB) * lda + m * KB + k % KB (lda: elements from one tile to the
+// next), of T likewise with ldb; tile
 // CBM (m) x 16*NTW (n); CBM/32 waves, wave w owns rows 32w..32w+31 (two m tiles) and all
 // columns.  LDS holds 16-byte runs [row][8 runs: hl 2 x run 4], run index XOR-swizzled
 // with sw8(row).  The k range may be split over grid.z: split z sums k in
@@ -629,7 +636,7 @@ __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restric
     const int id = t + CNT * r;
     const int row = id >> 3, hl = (id >> 2) & 1, run = id & 3;
     asrc[r] = hl ? Wl : Wh;
-    aoff[r] = static_cast<size_t>(m0 + row) * lda + k_lo + run * 8;
+    aoff[r] = static_cast<size_t>(k_lo / KB) * lda + static_cast<size_t>(m0 + row) * KB + run * 8;
     alo[r] = row * 8 + ((hl * 4 + run) ^ sw8(row));
   }
   size_t boff[BPER];
@@ -640,7 +647,7 @@ __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restric
     const int id = t + CNT * r;
     const int row = (id >> 3) < BN ? (id >> 3) : 0, hl = (id >> 2) & 1, run = id & 3;
     bsrc[r] = hl ? Tl : Th;
-    boff[r] = static_cast<size_t>(n0 + row) * ldb + k_lo + run * 8;
+    boff[r] = static_cast<size_t>(k_lo / KB) * ldb + static_cast<size_t>(n0 + row) * KB + run * 8;
     blo[r] = id < BRUNS ? row * 8 + ((hl * 4 + run) ^ sw8(row)) : -1;
   }
   const int fr = lane & 15, frun = lane >> 4;
@@ -668,12 +675,12 @@ __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restric
     const int ab = (st & 1) * ARUNS, bb = (st & 1) * BRUNS;
     const bool more = st + 1 < nsteps;
     if (more) {
-      const size_t ko = static_cast<size_t>(st + 1) * KB;
+      const size_t ka = static_cast<size_t>(st + 1) * lda, kb = static_cast<size_t>(st + 1) * ldb;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) ra[r] = *reinterpret_cast<const u32x4_t*>(asrc[r] + aoff[r] + ko);
+      for (int r = 0; r < 4; ++r) ra[r] = *reinterpret_cast<const u32x4_t*>(asrc[r] + aoff[r] + ka);
 #pragma unroll
       for (int r = 0; r < BPER; ++r)
-        if (blo[r] >= 0) rb[r] = *reinterpret_cast<const u32x4_t*>(bsrc[r] + boff[r] + ko);
+        if (blo[r] >= 0) rb[r] = *reinterpret_cast<const u32x4_t*>(bsrc[r] + boff[r] + kb);
     }
     bf16x8_t a[2][2];
 #pragma unroll
@@ -721,9 +728,9 @@ __global__ __launch_bounds__(CNT) void contract_bf16x3(const uint16_t* __restric
 // LDS holds 16-byte runs [row][8 runs: hl 2 x run 4] as above, double-buffered, but
 // with run q of row m at q ^ ((m >> 1) & 7): the sixteen rows of one fragment read still
 // hit distinct bank groups, and the swizzle repeats every 16 rows, so the fragments of
-// different row tiles lie at constant offsets from one address.  Every tile sums its k
-// steps in the order of contract_bf16x3.  grid (ncol/(64 NSUB), rows/256, splits),
-// block 512
+// different row tiles lie at constant offsets from one address.  Operands are tiled as
+// for contract_bf16x3, and every tile sums its k steps in the same order.
+// grid (ncol/(64 NSUB), rows/256, splits), block 512
 template <int NSUB>
 __global__ __launch_bounds__(512) void contract2_bf16x3(const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
                                                         long lda, const uint16_t* __restrict__ Th,
@@ -745,9 +752,9 @@ __global__ __launch_bounds__(512) void contract2_bf16x3(const uint16_t* __restri
   // staging: run id t + 512 r is row t/8 + 64 r of the tile, with the thread's own hi/lo
   // array and 8-element run; sw8 of the row does not depend on r
   const int srow = t >> 3, shl = (t >> 2) & 1, srun = t & 3;
-  const uint16_t* ap = (shl ? Wl : Wh) + static_cast<size_t>(m0 + srow) * lda + k_lo + srun * 8;
-  const uint16_t* bp = (shl ? Tl : Th) + static_cast<size_t>(n0 + srow) * ldb + k_lo + srun * 8;
-  const size_t astep = static_cast<size_t>(64) * lda, bstep = static_cast<size_t>(64) * ldb;
+  const uint16_t* ap = (shl ? Wl : Wh) + static_cast<size_t>(k_lo / KB) * lda + static_cast<size_t>(m0 + srow) * KB + srun * 8;
+  const uint16_t* bp = (shl ? Tl : Th) + static_cast<size_t>(k_lo / KB) * ldb + static_cast<size_t>(n0 + srow) * KB + srun * 8;
+  constexpr int astep = 64 * KB, bstep = 64 * KB;  // 64 rows on
   auto sw = [](int m) { return (m >> 1) & 7; };
   const int slo = srow * 8 + ((shl * 4 + srun) ^ sw(srow));  // + 512 r
   const int fr = lane & 15, frun = lane >> 4;
@@ -773,11 +780,11 @@ __global__ __launch_bounds__(512) void contract2_bf16x3(const uint16_t* __restri
     const int ab = (st & 1) * ARUNS, bb = (st & 1) * BRUNS;
     const bool more = st + 1 < nsteps;
     if (more) {
-      const size_t ko = static_cast<size_t>(st + 1) * KB;
+      const size_t ka = static_cast<size_t>(st + 1) * lda, kb = static_cast<size_t>(st + 1) * ldb;
 #pragma unroll
-      for (int r = 0; r < APER; ++r) ra[r] = *reinterpret_cast<const u32x4_t*>(ap + r * astep + ko);
+      for (int r = 0; r < APER; ++r) ra[r] = *reinterpret_cast<const u32x4_t*>(ap + r * astep + ka);
 #pragma unroll
-      for (int r = 0; r < BPER; ++r) rb[r] = *reinterpret_cast<const u32x4_t*>(bp + r * bstep + ko);
+      for (int r = 0; r < BPER; ++r) rb[r] = *reinterpret_cast<const u32x4_t*>(bp + r * bstep + kb);
     }
     bf16x8_t bh[NSUB], bl[NSUB];
 #pragma unroll
@@ -826,35 +833,40 @@ __global__ __launch_bounds__(512) void contract2_bf16x3(const uint16_t* __restri
 }
 
 // ---------------------------------------------------------------- slot order
-// Tn[n][256 q + 16 x + y] = T[n][256 q + split_slot(x, y)]: packed tau with the slots of
-// every block pair in natural order (16-bit words; rows of K).  grid (K/256, rows), block 256
-__global__ __launch_bounds__(256) void natural_slots_u16(const uint16_t* __restrict__ T, long K,
-                                                         uint16_t* __restrict__ Tn) {
-  const size_t base = static_cast<size_t>(blockIdx.y) * K + static_cast<size_t>(blockIdx.x) * 256;
+// Tn = T with the slots of every block pair in natural order: element (n, 256 q + 16 x + y)
+// of Tn is element (n, 256 q + split_slot(x, y)) of T (16-bit words; both tiled in 32
+// slots, ncol = gridDim.y rows).  grid (K/256, ncol), block 256
+__global__ __launch_bounds__(256) void natural_slots_u16(const uint16_t* __restrict__ T, uint16_t* __restrict__ Tn) {
+  const size_t n = blockIdx.y, ts = static_cast<size_t>(gridDim.y) * KB;
   const int nu = threadIdx.x;
-  Tn[base + nu] = T[base + split_slot(nu >> 4, nu & 15)];
+  const size_t kd = static_cast<size_t>(blockIdx.x) * 256 + nu;
+  const size_t ks = static_cast<size_t>(blockIdx.x) * 256 + split_slot(nu >> 4, nu & 15);
+  Tn[kd / KB * ts + n * KB + kd % KB] = T[ks / KB * ts + n * KB + ks % KB];
 }
 
 // ---------------------------------------------------------------- transpose
-// dst[c][r] = src[r][c] for r < rows, c < cols (16-bit words; src rows lds apart, dst rows
-// ldd apart), through 64 x 64 LDS tiles.  rows and cols are multiples of 64.
-// grid (cols/64, rows/64), block 256
-__global__ __launch_bounds__(256) void transpose_u16(const uint16_t* __restrict__ src, long lds, uint16_t* __restrict__ dst,
-                                                     long ldd) {
-  __shared__ uint16_t tile[64][66];
-  const long c0 = static_cast<long>(blockIdx.x) * 64, r0 = static_cast<long>(blockIdx.y) * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int r = ty + 4 * k;
-    tile[r][tx] = src[(r0 + r) * lds + c0 + tx];
-  }
+// dst (r', k') = src (k', r') for the 32 x 32 tiles of two tiled operands: src element
+// (r, k) at (k / 32) * sts + r * 32 + k % 32, dst element (r', k') at (k' / 32) * dts +
+// r' * 32 + k' % 32 (16-bit words).  One workgroup moves one contiguous 2 KB tile to
+// another.  grid (dst rows / 32, src rows / 32), block 256
+__global__ __launch_bounds__(256) void transpose_tiles_u16(const uint16_t* __restrict__ src, long sts,
+                                                           uint16_t* __restrict__ dst, long dts) {
+  __shared__ uint16_t tile[32][34];
+  const size_t kt = blockIdx.x, rt = blockIdx.y;  // src k tile (= dst row tile), src row tile
+  const int t = threadIdx.x, r = t >> 3, c = (t & 7) * 4;
+  const uint16_t* s = src + kt * sts + rt * (32 * KB);
+  uint16_t* d = dst + rt * dts + kt * (32 * KB);
+  const uint2 x = *reinterpret_cast<const uint2*>(s + r * KB + c);
+  tile[r][c] = static_cast<uint16_t>(x.x);
+  tile[r][c + 1] = static_cast<uint16_t>(x.x >> 16);
+  tile[r][c + 2] = static_cast<uint16_t>(x.y);
+  tile[r][c + 3] = static_cast<uint16_t>(x.y >> 16);
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int c = ty + 4 * k;
-    dst[(c0 + c) * ldd + r0 + tx] = tile[tx][c];
-  }
+  // dst row r (= src k c0 + r), columns c .. c + 3 (= src rows)
+  uint2 y;
+  y.x = static_cast<uint32_t>(tile[c][r]) | (static_cast<uint32_t>(tile[c + 1][r]) << 16);
+  y.y = static_cast<uint32_t>(tile[c + 2][r]) | (static_cast<uint32_t>(tile[c + 3][r]) << 16);
+  *reinterpret_cast<uint2*>(d + r * KB + c) = y;
 }
 
 // ---------------------------------------------------------------- host
@@ -1007,7 +1019,7 @@ static bool make_mplan(int o, int v, int naux, MPlan& p, size_t fit_bytes = 0) {
 }
 
 // The k range (extent K) is split `splits` ways (kz each) into partial outputs rows*ncol
-// apart.
+// apart.  lda, ldb: elements from one tile of KB k of the operand to the next.
 struct CArgs {
   const uint16_t *Wh, *Wl;
   long lda;
@@ -1067,7 +1079,8 @@ static void launch_build(const uint16_t* Bh, const uint16_t* Bl, const MPlan& p,
   const long k0 = D0 / GROUP_T, ntile = nT * (nT + 1) / 2 - k0 * (k0 + 1) / 2;
   const long ngroups = ntile * ((npairs + GROUP_AB - 1) / GROUP_AB);
   const long nwg = (ngroups + 7) / 8 * 8 * GROUP_AB * 2L * GROUP_T * GROUP_T;
-  build_w_bf16x3<<<dim3(static_cast<unsigned>(nwg)), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K, p.pm > 0 ? 1 : 0,
+  build_w_bf16x3<<<dim3(static_cast<unsigned>(nwg)), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, npairs * 256 * KB,
+                                                                   p.pm > 0 ? 1 : 0,
                                                                    pcd0, npairs, GROUP_AB, GROUP_T, Wph, Wpl, Wmh,
                                                                    Wml);
 }
@@ -1131,10 +1144,10 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
     }
     {
       ProfScope ps(s, "pack_tau_bf16", 0.0, 8.0 * oo * vv + 4.0 * (pv * p.po + pvm * p.pm));
-      pack_tau_bf16_kernel<<<dim3(p.nbp, p.NP), 256, 0, s>>>(tau, o, v, p.K, +1, Tph, Tpl);
+      pack_tau_bf16_kernel<<<dim3(p.nbp, p.NP), 256, 0, s>>>(tau, o, v, +1, Tph, Tpl);
       if ((rc = check_launch("pack_tau_bf16(+)"))) break;
       if (p.pm > 0) {
-        pack_tau_bf16_kernel<<<dim3(p.nbp, p.NM), 256, 0, s>>>(tau, o, v, p.K, -1, Tmh, Tml);
+        pack_tau_bf16_kernel<<<dim3(p.nbp, p.NM), 256, 0, s>>>(tau, o, v, -1, Tmh, Tml);
         if ((rc = check_launch("pack_tau_bf16(-)"))) break;
       }
     }
@@ -1156,16 +1169,16 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
       }
       if (ndiag > 0) {
         ProfScope ps(s, "build_w_bf16x3_diag", 2.0 * naux * vv * ld);
-        build_w_bf16x3_diag<<<dim3(p.nbp * 2, ndiag), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K,
+        build_w_bf16x3_diag<<<dim3(p.nbp * 2, ndiag), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, M * KB,
                                                                    p.pm > 0 ? 1 : 0, dy0, 0, Wph, Wpl, Wmh, Wml);
         if ((rc = check_launch("build_w_bf16x3_diag"))) break;
       }
       {
         ProfScope ps(s, "contract_bf16x3", 2.0 * (le * pv * p.po + lt * pvm * p.pm));
-        launch_contract(p.wide_p, p.ntw_p, CArgs{Wph, Wpl, p.K, Tph, Tpl, p.K, p.K, M, p.NP, S, zp, kzp, 0}, s);
+        launch_contract(p.wide_p, p.ntw_p, CArgs{Wph, Wpl, M * KB, Tph, Tpl, p.NP * KB, p.K, M, p.NP, S, zp, kzp, 0}, s);
         if ((rc = check_launch("contract_bf16x3(+)"))) break;
         if (p.pm > 0) {
-          launch_contract(p.wide_m, p.ntw_m, CArgs{Wmh, Wml, p.K, Tmh, Tml, p.K, p.K, M, p.NM, A, zm, kzm, 0}, s);
+          launch_contract(p.wide_m, p.ntw_m, CArgs{Wmh, Wml, M * KB, Tmh, Tml, p.NM * KB, p.K, M, p.NM, A, zm, kzm, 0}, s);
           if ((rc = check_launch("contract_bf16x3(-)"))) break;
         }
       }
@@ -1183,9 +1196,10 @@ int bf16x3_run(const double* B, long qs, long rs, const double* tau, int o, int 
 // ---------------------------------------------------------------- exchange symmetry
 // The exchange-symmetric ladder (factors symmetric in their virtual indices) in split
 // bf16: as the FP64 form, slab [P0, P1) builds the cd block pairs >= P0 only and uses
-// each built element twice.  W here is [ab slot][cd slot], so for the second product
+// each built element twice.  W here is W[ab slot][cd slot] (tiled in 32 cd slots), so
+// for the second product
 //   S2[cd][n] += sum_{ab in slab} W[ab][cd] T[n][ab]        (rows cd >= P1)
-// the block W[:, P1*256:] is first transposed (transpose_u16, 16-bit words) into
+// the block W[:, P1*256:] is first transposed (transpose_tiles_u16, 16-bit words) into
 // W2[cd][ab], after which the product is the contraction kernel with the slab's slice of
 // T, accumulating into S2 in slab order.  The ab index of W is in natural slot order and
 // its cd index in the split order (split_slot), so the second product sums against a
@@ -1243,18 +1257,18 @@ int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, d
     }
     {
       ProfScope ps(s, "pack_tau_bf16", 0.0, 0.0);
-      pack_tau_bf16_kernel<<<dim3(p.nbp, p.NP), 256, 0, s>>>(tau, o, v, p.K, +1, Tph, Tpl);
+      pack_tau_bf16_kernel<<<dim3(p.nbp, p.NP), 256, 0, s>>>(tau, o, v, +1, Tph, Tpl);
       if ((rc = check_launch("pack_tau_bf16(+)"))) break;
       if (p.pm > 0) {
-        pack_tau_bf16_kernel<<<dim3(p.nbp, p.NM), 256, 0, s>>>(tau, o, v, p.K, -1, Tmh, Tml);
+        pack_tau_bf16_kernel<<<dim3(p.nbp, p.NM), 256, 0, s>>>(tau, o, v, -1, Tmh, Tml);
         if ((rc = check_launch("pack_tau_bf16(-)"))) break;
       }
       const dim3 gp(static_cast<unsigned>(p.nbp), p.NP), gm(static_cast<unsigned>(p.nbp), p.NM);
-      natural_slots_u16<<<gp, 256, 0, s>>>(Tph, p.K, Tnph);
-      natural_slots_u16<<<gp, 256, 0, s>>>(Tpl, p.K, Tnpl);
+      natural_slots_u16<<<gp, 256, 0, s>>>(Tph, Tnph);
+      natural_slots_u16<<<gp, 256, 0, s>>>(Tpl, Tnpl);
       if (p.pm > 0) {
-        natural_slots_u16<<<gm, 256, 0, s>>>(Tmh, p.K, Tnmh);
-        natural_slots_u16<<<gm, 256, 0, s>>>(Tml, p.K, Tnml);
+        natural_slots_u16<<<gm, 256, 0, s>>>(Tmh, Tnmh);
+        natural_slots_u16<<<gm, 256, 0, s>>>(Tml, Tnml);
       }
       if ((rc = check_launch("natural_slots_u16"))) break;
     }
@@ -1275,7 +1289,7 @@ int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, d
       }
       if (ndiag > 0) {
         ProfScope ps(s, "build_w_bf16x3_diag", per_ab * ld);
-        build_w_bf16x3_diag<<<dim3((p.nbp - slab0) * 2, ndiag), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, p.K,
+        build_w_bf16x3_diag<<<dim3((p.nbp - slab0) * 2, ndiag), 512, 0, s>>>(Bh, Bl, p.Qp, p.vp, slab0, M * KB,
                                                                              p.pm > 0 ? 1 : 0, dy0, slab0, Wph, Wpl,
                                                                              Wmh, Wml);
         if ((rc = check_launch("build_w_bf16x3_diag"))) break;
@@ -1286,10 +1300,10 @@ int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, d
       const size_t c0 = static_cast<size_t>(slab0) * 256;  // first cd slot built for the slab
       {
         ProfScope ps(s, "contract_bf16x3", 2.0 * (le * ce * p.po + lt * ct * p.pm));
-        launch_contract(p.wide_p, p.ntw_p, CArgs{Wph + c0, Wpl + c0, p.K, Tph + c0, Tpl + c0, p.K, K1, M, p.NP, S, zp, kzp, 0}, s);
+        launch_contract(p.wide_p, p.ntw_p, CArgs{Wph + c0 * M, Wpl + c0 * M, M * KB, Tph + c0 * p.NP, Tpl + c0 * p.NP, p.NP * KB, K1, M, p.NP, S, zp, kzp, 0}, s);
         if ((rc = check_launch("contract_bf16x3(+)"))) break;
         if (p.pm > 0) {
-          launch_contract(p.wide_m, p.ntw_m, CArgs{Wmh + c0, Wml + c0, p.K, Tmh + c0, Tml + c0, p.K, K1, M, p.NM, A, zm, kzm, 0},
+          launch_contract(p.wide_m, p.ntw_m, CArgs{Wmh + c0 * M, Wml + c0 * M, M * KB, Tmh + c0 * p.NM, Tml + c0 * p.NM, p.NM * KB, K1, M, p.NM, A, zm, kzm, 0},
                           s);
           if ((rc = check_launch("contract_bf16x3(-)"))) break;
         }
@@ -1308,18 +1322,18 @@ int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, d
           ProfScope ps(s, "transpose_w_bf16", 0.0, 4.0 * nw * static_cast<double>(M) * rows2);
           uint16_t* Ws[4] = {Wph, Wpl, Wmh, Wml};
           for (int k = 0; k < nw; ++k)
-            transpose_u16<<<dim3(static_cast<unsigned>(rows2 / 64), static_cast<unsigned>(M / 64)), 256, 0, s>>>(
-                Ws[k] + c1, p.K, W2[k], M);
-          if ((rc = check_launch("transpose_u16"))) break;
+            transpose_tiles_u16<<<dim3(static_cast<unsigned>(rows2 / 32), static_cast<unsigned>(M / 32)), 256, 0, s>>>(
+                Ws[k] + c1 * M, M * KB, W2[k], rows2 * KB);
+          if ((rc = check_launch("transpose_tiles_u16"))) break;
         }
         double le2, lt2, ld2;
         count_pairs(v, p1, p.nbp - p1, le2, lt2, ld2);
         ProfScope ps(s, "contract2_bf16x3", 2.0 * (le2 * le * p.po + lt2 * lt * p.pm));
-        launch_contract(p.wide_p, p.ntw_p, CArgs{W2[0], W2[1], M, Tnph + c0, Tnpl + c0, p.K, M, rows2, p.NP,
+        launch_contract(p.wide_p, p.ntw_p, CArgs{W2[0], W2[1], rows2 * KB, Tnph + c0 * p.NP, Tnpl + c0 * p.NP, p.NP * KB, M, rows2, p.NP,
                                        S2 + c1 * p.NP, 1, M, accum}, s);
         if ((rc = check_launch("contract2_bf16x3(+)"))) break;
         if (p.pm > 0) {
-          launch_contract(p.wide_m, p.ntw_m, CArgs{W2[2], W2[3], M, Tnmh + c0, Tnml + c0, p.K, M, rows2, p.NM,
+          launch_contract(p.wide_m, p.ntw_m, CArgs{W2[2], W2[3], rows2 * KB, Tnmh + c0 * p.NM, Tnml + c0 * p.NM, p.NM * KB, M, rows2, p.NM,
                                          A2 + c1 * p.NM, 1, M, accum}, s);
           if ((rc = check_launch("contract2_bf16x3(-)"))) break;
         }
