@@ -869,6 +869,31 @@ __global__ __launch_bounds__(256) void transpose_tiles_u16(const uint16_t* __res
   *reinterpret_cast<uint2*>(d + r * KB + c) = y;
 }
 
+// ---------------------------------------------------------------- split sums
+// dst[i] = (accum ? dst[i] : 0) + (sum over z < nz of P[z * zs + i], added in z order),
+// for i < n (n and zs multiples of 4, arrays 16-byte aligned).  Four partials are read
+// together (clamped to a valid split, the extra ones not added).
+// grid ceil(n / 1024), block 256
+__global__ __launch_bounds__(256) void sum_splits_f32(const float* __restrict__ P, long zs, int nz, long n,
+                                                      float* __restrict__ dst, int accum) {
+  const long i = (static_cast<long>(blockIdx.x) * 256 + threadIdx.x) * 4;
+  if (i >= n) return;
+  f32x4_t acc = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int z = 0; z < nz; z += 4) {
+    f32x4_t x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const long zk = z + k < nz ? z + k : nz - 1;
+      x[k] = *reinterpret_cast<const f32x4_t*>(P + zk * zs + i);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (z + k < nz) acc = z + k == 0 ? x[k] : acc + x[k];
+  }
+  f32x4_t* d = reinterpret_cast<f32x4_t*>(dst + i);
+  *d = accum ? *d + acc : acc;
+}
+
 // ---------------------------------------------------------------- host
 // Workgroups of the contraction kernel for (wide, ntw) resident at once on the device.
 static long contract_slots(int wide, int ntw) {
@@ -912,6 +937,20 @@ static int contract_splits(int wide, int ntw, int ncol, long rows, long K, long&
   kz = (K + z - 1) / z;
   kz = (kz + KB - 1) / KB * KB;
   return static_cast<int>((K + kz - 1) / kz);
+}
+
+// Splits of the exchange-symmetric form's second product (k = the slab's M slots, rows2
+// rows): enough to fill the chip once, at least 8 steps per split, balanced as above,
+// and no more than `avail` elements of partial sums (rows2 * ncol per split) hold.
+static int second_splits(int wide, int ntw, int ncol, long rows2, long M, size_t avail, long& kz) {
+  const long nwg = (ncol / (16 * ntw)) * (rows2 / CBM);
+  const long slots = contract_slots(wide, ntw);
+  const long zmax = std::max(1L, std::min(M / (8 * KB), static_cast<long>(avail / (static_cast<size_t>(rows2) * ncol))));
+  long z = std::max(1L, std::min((slots + nwg - 1) / nwg, zmax));
+  z = balance_splits(nwg, slots, M, KB, z, zmax);
+  kz = (M + z - 1) / z;
+  kz = (kz + KB - 1) / KB * KB;
+  return static_cast<int>((M + kz - 1) / kz);
 }
 
 struct MPlan {
@@ -1328,15 +1367,31 @@ int bf16x3_run_sym(const double* B, const double* tau, int o, int v, int naux, d
         }
         double le2, lt2, ld2;
         count_pairs(v, p1, p.nbp - p1, le2, lt2, ld2);
-        ProfScope ps(s, "contract2_bf16x3", 2.0 * (le2 * le * p.po + lt2 * lt * p.pm));
-        launch_contract(p.wide_p, p.ntw_p, CArgs{W2[0], W2[1], rows2 * KB, Tnph + c0 * p.NP, Tnpl + c0 * p.NP, p.NP * KB, M, rows2, p.NP,
-                                       S2 + c1 * p.NP, 1, M, accum}, s);
-        if ((rc = check_launch("contract2_bf16x3(+)"))) break;
-        if (p.pm > 0) {
-          launch_contract(p.wide_m, p.ntw_m, CArgs{W2[2], W2[3], rows2 * KB, Tnmh + c0 * p.NM, Tnml + c0 * p.NM, p.NM * KB, M, rows2, p.NM,
-                                         A2 + c1 * p.NM, 1, M, accum}, s);
-          if ((rc = check_launch("contract2_bf16x3(-)"))) break;
+        ProfScope ps(s, "second_product_bf16x3", 2.0 * (le2 * le * p.po + lt2 * lt * p.pm));
+        // split over the slab's slots into the partial buffers S and A (free once the
+        // first product is unpacked), then added into S2 and A2 in split order; one
+        // split accumulates into S2 and A2 directly
+        const int nside = p.pm > 0 ? 2 : 1;
+        for (int side = 0; side < nside && rc == RI_OK; ++side) {
+          const bool plus = side == 0;
+          const int wide = plus ? p.wide_p : p.wide_m, ntw = plus ? p.ntw_p : p.ntw_m, ncol = plus ? p.NP : p.NM;
+          float* part = plus ? S : A;
+          float* dst = (plus ? S2 : A2) + c1 * ncol;
+          long kz2;
+          const int z2 = second_splits(wide, ntw, ncol, rows2, M, plus ? p.n_S : p.n_A, kz2);
+          const uint16_t* Th = plus ? Tnph : Tnmh;
+          const uint16_t* Tl = plus ? Tnpl : Tnml;
+          const CArgs ca{W2[plus ? 0 : 2], W2[plus ? 1 : 3], rows2 * KB, Th + c0 * ncol, Tl + c0 * ncol, ncol * KB, M,
+                         rows2, ncol, z2 > 1 ? part : dst, z2, kz2, z2 > 1 ? 0 : accum};
+          launch_contract(wide, ntw, ca, s);
+          if ((rc = check_launch(plus ? "second product (+)" : "second product (-)"))) break;
+          if (z2 > 1) {
+            const long n = rows2 * ncol;
+            sum_splits_f32<<<dim3(static_cast<unsigned>((n + 1023) / 1024)), 256, 0, s>>>(part, n, z2, n, dst, accum);
+            rc = check_launch("sum_splits_f32");
+          }
         }
+        if (rc != RI_OK) break;
       }
     }
     if (rc == RI_OK && first_p1 >= 0) {
