@@ -164,7 +164,11 @@ int ri_ppl_sym_ex(const double* B_vv, const double* tau, int o, int v, int naux,
  * 0 on invalid arguments. */
 double ri_ppl_sym_flops(int o, int v, int naux);
 
-/* Workspace bytes ri_ppl_ex needs for these sizes (0 on invalid arguments). */
+/* Workspace bytes ri_ppl_ex needs for these sizes (0 on invalid arguments).  The
+ * partial sums of the contraction's k splits are part of it, and their number follows
+ * the current device (its compute units and the contraction kernel's occupancy): ask
+ * with the device current that ri_ppl_ex will run on.  Without a device the count
+ * assumes 256 compute units. */
 size_t ri_ppl_workspace_bytes(int o, int v, int naux, int precision);
 
 /* Algorithmic floating-point operation count of one ladder call as executed
