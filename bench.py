@@ -6,11 +6,15 @@ One step = one ladder call (eq. pp-Ladder-0): the tau+- packing, the tile-by-til
 with every input already resident in HBM.  Default workload: o=48, v=768, naux=2304
 (seed 4; B_vv, tau and R 10.9 GB each), tau = MP2 t2 + t1 (x) t1, timed in the split-bf16
 arithmetic the ladder runs in inside CCSD; then the same call in FP64 (one untimed and
---fp64-steps timed calls) for the mixed-vs-FP64 comparison.  Prints one JSON line on
-stdout.
+--fp64-steps timed calls) for the mixed-vs-FP64 comparison.  The metric's second half,
+time to converged E_corr, is the `ttc` object: closed-shell RI-CCSD at o=32, v=512,
+naux=1536 (seed 3, Naux-scaled generator) from the MP2 guess to max |Omega| <= 1e-8
+and |dE| <= 1e-9, once with the FP64 ladder and once with the split-bf16 ladder (other
+terms FP64), wall time of each solve and the energy difference (--no-ttc skips it).
+Prints one JSON line on stdout.
 
   python bench.py [--steps K] [--warmup W] [--workload c4|c2] [--precision bf16x3|fp64|fp32]
-                  [--fp64-steps N]
+                  [--fp64-steps N] [--no-ttc]
 """
 from __future__ import annotations
 
@@ -87,6 +91,39 @@ def make_inputs(workload: str):
     del B, t2
     torch.cuda.synchronize()
     return s, B_vv, tau
+
+
+def ttc_leg():
+    """Time to converged E_corr at o=32 v=512 naux=1536 with the FP64 and with the
+    split-bf16 ladder (the other terms FP64 in both), each solve timed whole (its own
+    setup included, inputs already on the device)."""
+    import torch
+
+    from paper_1810_08142_amd import ccsd
+    from paper_1810_08142_amd.synthetic import CONFIGS, draw_system
+    cfg = CONFIGS["c3"]
+    s = draw_system(cfg["o"], cfg["v"], cfg["naux"], seed=cfg["seed"], scale="naux")
+    B = torch.from_numpy(s.B).to("cuda")
+    eps = torch.from_numpy(s.eps).to("cuda")
+    torch.cuda.synchronize()
+    runs = {}
+    for prec in ("fp64", "bf16x3"):
+        log(f"[bench] time to converged E_corr, {prec} ladder")
+        _, _, rep = ccsd.solve(B, eps, s.o, max_iter=100, tol=1e-8, tol_energy=1e-9, ppl_precision=prec,
+                               check_fp64=True)
+        runs[prec] = rep
+    f, m = runs["fp64"], runs["bf16x3"]
+    de = m.e_corr - f.e_corr
+    return {"workload": f"c3: RI-CCSD o={s.o} v={s.v} naux={s.naux}, seed {s.seed}, scale {s.scale:.4g}",
+            "tol": 1e-8, "tol_energy": 1e-9,
+            "fp64": {"seconds": round(f.seconds_total, 3), "ladder_seconds": round(f.seconds_ppl, 3),
+                     "iterations": f.iterations, "converged": bool(f.converged), "e_corr": f.e_corr},
+            "mixed": {"ladder": "bf16x3", "seconds": round(m.seconds_total, 3),
+                      "ladder_seconds": round(m.seconds_ppl, 3), "iterations": m.iterations,
+                      "converged": bool(m.converged), "e_corr": m.e_corr,
+                      "fp64_residual_inf": m.residual_inf_fp64},
+            "speedup_mixed_vs_fp64": round(f.seconds_total / m.seconds_total, 3),
+            "delta_e_corr": de, "within_1_uEh": bool(abs(de) <= 1e-6)}
 
 
 def cpu_baseline(s, workload: str, flops_call: float, seconds: float):
@@ -241,6 +278,7 @@ def main():
                     help="timed FP64 calls after the timed steps (after one untimed call); 0 skips the leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttc", action="store_true", help="skip the time-to-converged-E_corr leg")
     ap.add_argument("--cpu-plan", action="store_true",
                     help="only time the CPU oracle on its plan of workloads (all cores and one core) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -293,8 +331,13 @@ def main():
                 "steps": args.fp64_steps, "warmup": 1, "speedup_of_timed_precision": round(ms64 / ms, 3),
                 "roofline": roofline_of(k64, "fp64", args.workload),
                 "phases_ms": {k["name"]: round(k["ms"] / args.fp64_steps, 4) for k in k64}}
-    del R, tau
+    del R, tau, B_vv
     torch.cuda.synchronize()
+
+    ttc = None
+    if not args.no_ttc:
+        ttc = ttc_leg()
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -320,6 +363,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_same_call": fp64,
+        "ttc": ttc,
         "phases_ms": phases,
     }
     print(json.dumps(out), flush=True)
